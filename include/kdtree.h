@@ -1,0 +1,148 @@
+/*
+ * kdtree.h -- C ABI of libkdtree.so: exact find-closest-point (fcp) and
+ * k-nearest-neighbour (kNN) queries over left-balanced, complete k-d trees
+ * stored in level order, traversed on an AMD Instinct MI355X (gfx950) with
+ * the stack-free two-integer state machine of Wald, "A Stack-Free Traversal
+ * Algorithm for Left-Balanced k-d Trees" (arXiv 2210.12859), Sec. 3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named points / queries / out_* / r0 / visited are DEVICE
+ *    pointers (hipMalloc'd or torch CUDA tensors) unless stated otherwise.
+ *    points and queries are float32, row-major [n][dim].
+ *  - Results are int32 caller indices (0..N-1 of the points passed to
+ *    kd_build, never tree positions) and float32 squared distances, [Q][k]
+ *    row-major in the caller's query order, each row ascending by the key
+ *    (d2, index).  Empty slots hold index -1 and d2 = +inf.
+ *  - Squared distances are IEEE binary32: d2 = ((dx0*dx0 + dx1*dx1) + ...)
+ *    with dx_j = q_j - p_j, left to right, no fused multiply-add, no
+ *    flush-to-zero.  A point is eligible when d2 <= fl32(maxRadius*maxRadius)
+ *    (inclusive; maxRadius = +inf means unbounded).  Ties in d2 go to the
+ *    smaller point index.
+ *  - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *    Query calls are asynchronous on it; the caller keeps every pointer alive
+ *    and unmodified until the stream has reached the call.
+ *  - Errors: every call returns a kd_status.  Arguments are validated before
+ *    anything is enqueued; on error no output is touched.  kd_last_error()
+ *    gives a thread-local message for the last non-OK status.  A device fault
+ *    of an earlier asynchronous call surfaces as KD_EHIP from a later call.
+ *  - Trees and models are immutable after creation; concurrent queries on
+ *    different streams against one tree are safe.
+ */
+#ifndef KDTREE_H
+#define KDTREE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kd_tree_s* kd_tree;   /* opaque, owned by the library */
+typedef struct kd_model_s* kd_model; /* opaque, owned by the library */
+typedef void* kd_stream;             /* a hipStream_t */
+
+typedef enum {
+    KD_OK = 0,
+    KD_EINVAL = -1,       /* bad argument; nothing enqueued */
+    KD_ENOMEM = -2,       /* device or host allocation failed */
+    KD_EHIP = -3,         /* HIP runtime error (possibly from an earlier call) */
+    KD_EUNSUPPORTED = -4  /* valid request this build does not implement */
+} kd_status;
+
+/* Largest supported k; k values other than 1,4,8,16,32,64 are served by the
+ * next larger compiled list size, returning its first k entries (exact: the
+ * k-best list is a prefix of any longer one). */
+#define KD_MAX_K 64
+/* Largest point count: child indices 2n+2 must fit in int32 (Sec. 3.2). */
+#define KD_MAX_POINTS (1LL << 30)
+
+/* Launch tuning.  Every setting gives byte-identical results; only speed
+ * differs.  A zero-initialised struct, or NULL, means "tuned defaults"
+ * (the autotuner's cached choice for the tree when kd_autotune ran). */
+typedef struct {
+    int block;       /* threads per workgroup: 64, 128 or 256; 0 = default */
+    int lds_levels;  /* top tree levels staged in LDS, 0..12; -1 = default */
+    int sort_bits;   /* Morton bits the queries are sorted on before traversal:
+                        0 (no reordering), 8, 16, 24 or 32 (all bits); -1 = default */
+    int waves_per_cu;/* persistent grid size in waves per compute unit; 0 = default */
+} kd_opts;
+
+/* ------------------------------------------------------------ tree build */
+
+/* Builds the canonical left-balanced, complete k-d tree over N points of
+ * dimension dim (paper Sec. 1 and Sec. 3 assumption list): level-order array,
+ * children of node n at 2n+1 and 2n+2, split dimension floor(log2(n+1)) mod
+ * dim, and at every node the element of rank leftSize(|S|) of its subtree set
+ * S ordered by (split coordinate, caller index) -- the unique tree once ties
+ * are broken by index (Sec. 4 notes that any builder yields the same tree).
+ *   points : device, float32 [N][dim]; read only.  NaN or +-inf -> KD_EINVAL.
+ *   N      : 0 <= N <= KD_MAX_POINTS.  N = 0 gives an empty tree whose queries
+ *            return all -1.
+ *   dim    : 2, 3 or 4.
+ *   out    : receives the tree; free with kd_tree_free.
+ * Synchronises the stream (the build runs on the host in this version). */
+kd_status kd_build(const float* points, int64_t N, int dim, kd_stream stream, kd_tree* out);
+
+/* Same, from a HOST float32 [N][dim] array (no device read of the input). */
+kd_status kd_build_host(const float* host_points, int64_t N, int dim, kd_tree* out);
+
+/* The same canonical level-order permutation computed on the host only (no
+ * device involved): host_order[pos] = caller index of the point at tree
+ * position pos.  host_points is HOST float32 [N][dim], 1 <= dim <= 8.
+ * Used to build trees for other consumers and to check the builder. */
+kd_status kd_build_order_host(const float* host_points, int64_t N, int dim, int32_t* host_order);
+
+kd_status kd_tree_free(kd_tree t);
+
+/* Tree facts.  Any out pointer may be NULL. */
+kd_status kd_tree_info(kd_tree t, int64_t* N, int* dim, float* bbox_lo4, float* bbox_hi4);
+
+/* Copies the level-order permutation to HOST memory: order[pos] = caller
+ * index of the point at tree position pos; order has N entries. */
+kd_status kd_tree_order(kd_tree t, int32_t* host_order);
+
+/* --------------------------------------------------------------- queries */
+
+/* find-closest-point (paper Sec. 4, the fcp kernel) = kNN with k = 1.
+ *   queries : device float32 [Q][dim];  Q >= 0.
+ *   maxRadius : >= 0 or +inf; NaN or negative -> KD_EINVAL.
+ *   out_idx : device int32 [Q];  out_d2 : device float32 [Q] or NULL. */
+kd_status kd_fcp(kd_tree t, const float* queries, int64_t Q, float maxRadius,
+                 int32_t* out_idx, float* out_d2, kd_stream stream);
+
+/* k nearest neighbours (paper Sec. 4, the knn kernel, bounded or unbounded).
+ *   k : 1 <= k <= KD_MAX_K.   out_idx : device int32 [Q][k];
+ *   out_d2 : device float32 [Q][k] or NULL.  Other arguments as kd_fcp. */
+kd_status kd_knn(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius,
+                 int32_t* out_idx, float* out_d2, kd_stream stream);
+
+/* kd_knn with launch options and an optional per-query count of processed
+ * nodes (first visits of existing nodes; the paper's processNode calls):
+ *   visited : device uint32 [Q] or NULL.   opts : may be NULL. */
+kd_status kd_knn_ex(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius,
+                    int32_t* out_idx, float* out_d2, uint32_t* visited,
+                    const kd_opts* opts, kd_stream stream);
+
+/* ------------------------------------------------------------ timing */
+
+/* Kernel timing for benchmarks.  While enabled, every launch of the library's
+ * traversal kernel ("traverse") and of its other stages is bracketed by
+ * hipEvents recorded on the stream it runs on.  kd_timing_collect waits for
+ * the recorded events of one kernel name, returns the summed elapsed time in
+ * milliseconds and the launch count, and clears all recorded events. */
+kd_status kd_timing_enable(int on);
+kd_status kd_timing_collect(const char* kernel, double* total_ms, int64_t* launches);
+
+/* ------------------------------------------------------------ status */
+
+const char* kd_status_str(kd_status s);
+const char* kd_last_error(void);
+/* Library version string, e.g. "kdtree-gfx950 0.1". */
+const char* kd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KDTREE_H */

@@ -1,0 +1,371 @@
+// kd_api.cpp -- the C ABI of libkdtree: argument validation, error state,
+// tree objects, per-stream scratch, and dispatch into the HIP pipeline.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "kd_internal.h"
+
+namespace kd {
+
+namespace {
+thread_local std::string g_last_error;
+
+std::mutex g_dev_mu;
+std::map<int, DeviceInfo> g_dev;
+
+struct ScratchBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_scratch_mu;
+std::map<std::pair<int, kd_stream>, ScratchBuf> g_scratch;
+}  // namespace
+
+kd_status set_error(kd_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+kd_status hip_error(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? KD_ENOMEM : KD_EHIP;
+}
+
+const DeviceInfo& device_info(int device) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev.find(device);
+    if (it != g_dev.end()) return it->second;
+    DeviceInfo di;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) == hipSuccess) {
+        di.cus = p.multiProcessorCount;
+        di.lds_bytes = int(p.sharedMemPerBlock);
+    }
+    return g_dev.emplace(device, di).first->second;
+}
+
+namespace {
+struct TimedLaunch {
+    std::string kernel;
+    hipEvent_t a, b;
+};
+std::mutex g_timing_mu;
+bool g_timing_on = false;
+std::vector<TimedLaunch> g_timed;
+}  // namespace
+
+bool timing_enabled() {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    return g_timing_on;
+}
+
+kd_status timing_begin(hipStream_t st, hipEvent_t* ev) {
+    *ev = nullptr;
+    if (!timing_enabled()) return KD_OK;
+    KD_HIP(hipEventCreate(ev));
+    KD_HIP(hipEventRecord(*ev, st));
+    return KD_OK;
+}
+
+kd_status timing_end(hipStream_t st, hipEvent_t ev0, const char* kernel) {
+    if (!ev0) return KD_OK;
+    hipEvent_t ev1;
+    KD_HIP(hipEventCreate(&ev1));
+    KD_HIP(hipEventRecord(ev1, st));
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timed.push_back({kernel, ev0, ev1});
+    return KD_OK;
+}
+
+kd_status scratch(kd_stream stream, size_t bytes, void** out) {
+    int dev = 0;
+    KD_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchBuf& b = g_scratch[{dev, stream}];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            // the stream may still use the old buffer
+            KD_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+            KD_HIP(hipFree(b.ptr));
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        size_t sz = bytes < (1u << 20) ? (1u << 20) : bytes + bytes / 4;
+        KD_HIP(hipMalloc(&b.ptr, sz));
+        b.bytes = sz;
+    }
+    *out = b.ptr;
+    return KD_OK;
+}
+
+namespace {
+
+template <int D>
+void pack_records(const float* pts, const int32_t* order, int64_t N, std::vector<unsigned char>& out) {
+    out.resize(size_t(N) * sizeof(NodeRec<D>));
+    NodeRec<D>* r = reinterpret_cast<NodeRec<D>*>(out.data());
+    for (int64_t pos = 0; pos < N; ++pos) {
+        const int32_t i = order[pos];
+        for (int j = 0; j < D; ++j) r[pos].c[j] = pts[int64_t(i) * D + j];
+        r[pos].idx = i;
+    }
+}
+
+kd_status build_from_host(const float* hp, int64_t N, int dim, kd_tree* out) {
+    if (!out) return set_error(KD_EINVAL, "kd_build: out is NULL");
+    if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build: N out of range [0, 2^30]");
+    if (dim < 2 || dim > 4) return set_error(KD_EINVAL, "kd_build: dim must be 2, 3 or 4");
+    if (N > 0 && !hp) return set_error(KD_EINVAL, "kd_build: points is NULL");
+    for (int64_t i = 0; i < N * dim; ++i)
+        if (!std::isfinite(hp[i])) return set_error(KD_EINVAL, "kd_build: points contain NaN or inf");
+    std::unique_ptr<kd_tree_s> t(new (std::nothrow) kd_tree_s);
+    if (!t) return set_error(KD_ENOMEM, "kd_build: host allocation");
+    t->N = N;
+    t->dim = dim;
+    KD_HIP(hipGetDevice(&t->device));
+    for (int j = 0; j < 4; ++j) { t->lo[j] = 0; t->hi[j] = 0; }
+    if (N > 0) {
+        for (int j = 0; j < dim; ++j) { t->lo[j] = hp[j]; t->hi[j] = hp[j]; }
+        for (int64_t i = 1; i < N; ++i)
+            for (int j = 0; j < dim; ++j) {
+                float v = hp[i * dim + j];
+                if (v < t->lo[j]) t->lo[j] = v;
+                if (v > t->hi[j]) t->hi[j] = v;
+            }
+    }
+    try {
+        t->order.resize(size_t(N));
+    } catch (...) {
+        return set_error(KD_ENOMEM, "kd_build: host allocation");
+    }
+    build_level_order(hp, N, dim, t->order.data(), 0);
+    if (N > 0) {
+        std::vector<unsigned char> recs;
+        if (dim == 2) pack_records<2>(hp, t->order.data(), N, recs);
+        else if (dim == 3) pack_records<3>(hp, t->order.data(), N, recs);
+        else pack_records<4>(hp, t->order.data(), N, recs);
+        KD_HIP(hipMalloc(&t->d_nodes, recs.size()));
+        hipError_t e = hipMemcpy(t->d_nodes, recs.data(), recs.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(t->d_nodes);
+            return hip_error(e, "kd_build: upload");
+        }
+    }
+    *out = t.release();
+    return KD_OK;
+}
+
+kd_status check_query_args(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius,
+                           const int32_t* out_idx, const char* fn) {
+    std::string f(fn);
+    if (Q < 0 || Q >= (int64_t(1) << 31)) return set_error(KD_EINVAL, f + ": Q out of range [0, 2^31)");
+    if (k < 1 || k > KD_MAX_K) return set_error(KD_EINVAL, f + ": k out of range [1, 64]");
+    if (std::isnan(maxRadius) || maxRadius < 0.0f) return set_error(KD_EINVAL, f + ": maxRadius must be >= 0 or +inf");
+    if (!t) return set_error(KD_EINVAL, f + ": tree is NULL");
+    if (Q > 0 && !queries) return set_error(KD_EINVAL, f + ": queries is NULL");
+    if (Q > 0 && !out_idx) return set_error(KD_EINVAL, f + ": out_idx is NULL");
+    return KD_OK;
+}
+
+__global__ void fill_empty(int32_t* idx, float* d2, int64_t n) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) {
+        idx[i] = -1;
+        if (d2) d2[i] = __builtin_inff();
+    }
+}
+
+__global__ void fill_zero_u32(uint32_t* p, int64_t n) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, QueryPlan& p) {
+    p.k = k;
+    p.K = k_template(k);
+    float r = maxRadius;
+    p.R2 = r * r;  // binary32 product; +inf stays +inf
+    kd_opts use{0, -1, -1, 0};
+    if (o) use = *o;
+    if (use.block == 0) use.block = 256;
+    if (use.lds_levels < 0) use.lds_levels = 10;
+    if (use.sort_bits < 0) use.sort_bits = 32;
+    if (use.waves_per_cu == 0) use.waves_per_cu = 8;
+    if (use.block != 64 && use.block != 128 && use.block != 256)
+        return set_error(KD_EINVAL, "opts.block must be 64, 128 or 256");
+    if (use.lds_levels > 13) return set_error(KD_EINVAL, "opts.lds_levels must be <= 13");
+    if (use.sort_bits != 0 && use.sort_bits != 8 && use.sort_bits != 16 && use.sort_bits != 24 &&
+        use.sort_bits != 32)
+        return set_error(KD_EINVAL, "opts.sort_bits must be 0, 8, 16, 24 or 32");
+    if (use.waves_per_cu < 1 || use.waves_per_cu > 32) return set_error(KD_EINVAL, "opts.waves_per_cu must be in 1..32");
+    p.block = use.block;
+    p.lds_levels = use.lds_levels;
+    p.sort_bits = use.sort_bits;
+    p.waves_per_cu = use.waves_per_cu;
+    return KD_OK;
+}
+
+}  // namespace
+
+kd_status knn_entry(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius, int32_t* out_idx,
+                    float* out_d2, uint32_t* visited, const kd_opts* opts, kd_stream stream, const char* fn) {
+    kd_status s = check_query_args(t, queries, Q, k, maxRadius, out_idx, fn);
+    if (s != KD_OK) return s;
+    QueryPlan plan;
+    s = resolve_plan(t, k, maxRadius, opts, plan);
+    if (s != KD_OK) return s;
+    if (Q == 0) return KD_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (t->N == 0) {
+        // empty tree: every slot is empty; the traversal is never entered
+        int64_t n = Q * k;
+        hipLaunchKernelGGL(fill_empty, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, out_idx, out_d2, n);
+        KD_HIP(hipGetLastError());
+        if (visited) {
+            hipLaunchKernelGGL(fill_zero_u32, dim3(unsigned((Q + 255) / 256)), dim3(256), 0, st, visited, Q);
+            KD_HIP(hipGetLastError());
+        }
+        return KD_OK;
+    }
+    return run_knn(t, queries, Q, plan, out_idx, out_d2, visited, stream);
+}
+
+}  // namespace kd
+
+using namespace kd;
+
+extern "C" {
+
+kd_status kd_build_host(const float* host_points, int64_t N, int dim, kd_tree* out) {
+    try {
+        return build_from_host(host_points, N, dim, out);
+    } catch (const std::exception& e) {
+        return set_error(KD_ENOMEM, std::string("kd_build: ") + e.what());
+    }
+}
+
+kd_status kd_build(const float* points, int64_t N, int dim, kd_stream stream, kd_tree* out) {
+    if (!out) return set_error(KD_EINVAL, "kd_build: out is NULL");
+    if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build: N out of range [0, 2^30]");
+    if (dim < 2 || dim > 4) return set_error(KD_EINVAL, "kd_build: dim must be 2, 3 or 4");
+    if (N > 0 && !points) return set_error(KD_EINVAL, "kd_build: points is NULL");
+    try {
+        std::vector<float> host(size_t(N) * dim);
+        if (N > 0) {
+            KD_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+            KD_HIP(hipMemcpy(host.data(), points, host.size() * sizeof(float), hipMemcpyDeviceToHost));
+        }
+        return build_from_host(host.data(), N, dim, out);
+    } catch (const std::exception& e) {
+        return set_error(KD_ENOMEM, std::string("kd_build: ") + e.what());
+    }
+}
+
+kd_status kd_build_order_host(const float* host_points, int64_t N, int dim, int32_t* host_order) {
+    if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build_order_host: N out of range [0, 2^30]");
+    if (dim < 1 || dim > 8) return set_error(KD_EINVAL, "kd_build_order_host: dim must be in 1..8");
+    if (N > 0 && (!host_points || !host_order)) return set_error(KD_EINVAL, "kd_build_order_host: NULL pointer");
+    try {
+        build_level_order(host_points, N, dim, host_order, 0);
+    } catch (const std::exception& e) {
+        return set_error(KD_ENOMEM, std::string("kd_build_order_host: ") + e.what());
+    }
+    return KD_OK;
+}
+
+kd_status kd_tree_free(kd_tree t) {
+    if (!t) return KD_OK;
+    if (t->d_nodes) (void)hipFree(t->d_nodes);
+    delete t;
+    return KD_OK;
+}
+
+kd_status kd_tree_info(kd_tree t, int64_t* N, int* dim, float* lo4, float* hi4) {
+    if (!t) return set_error(KD_EINVAL, "kd_tree_info: tree is NULL");
+    if (N) *N = t->N;
+    if (dim) *dim = t->dim;
+    if (lo4) std::memcpy(lo4, t->lo, sizeof(t->lo));
+    if (hi4) std::memcpy(hi4, t->hi, sizeof(t->hi));
+    return KD_OK;
+}
+
+kd_status kd_tree_order(kd_tree t, int32_t* host_order) {
+    if (!t) return set_error(KD_EINVAL, "kd_tree_order: tree is NULL");
+    if (t->N > 0 && !host_order) return set_error(KD_EINVAL, "kd_tree_order: host_order is NULL");
+    if (t->N > 0) std::memcpy(host_order, t->order.data(), size_t(t->N) * sizeof(int32_t));
+    return KD_OK;
+}
+
+kd_status kd_fcp(kd_tree t, const float* queries, int64_t Q, float maxRadius, int32_t* out_idx, float* out_d2,
+                 kd_stream stream) {
+    return knn_entry(t, queries, Q, 1, maxRadius, out_idx, out_d2, nullptr, nullptr, stream, "kd_fcp");
+}
+
+kd_status kd_knn(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius, int32_t* out_idx,
+                 float* out_d2, kd_stream stream) {
+    return knn_entry(t, queries, Q, k, maxRadius, out_idx, out_d2, nullptr, nullptr, stream, "kd_knn");
+}
+
+kd_status kd_knn_ex(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius, int32_t* out_idx,
+                    float* out_d2, uint32_t* visited, const kd_opts* opts, kd_stream stream) {
+    return knn_entry(t, queries, Q, k, maxRadius, out_idx, out_d2, visited, opts, stream, "kd_knn_ex");
+}
+
+const char* kd_status_str(kd_status s) {
+    switch (s) {
+        case KD_OK: return "KD_OK";
+        case KD_EINVAL: return "KD_EINVAL: invalid argument";
+        case KD_ENOMEM: return "KD_ENOMEM: out of memory";
+        case KD_EHIP: return "KD_EHIP: HIP runtime error";
+        case KD_EUNSUPPORTED: return "KD_EUNSUPPORTED: not supported";
+    }
+    return "unknown kd_status";
+}
+
+const char* kd_last_error(void) { return g_last_error.c_str(); }
+
+kd_status kd_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timing_on = on != 0;
+    return KD_OK;
+}
+
+kd_status kd_timing_collect(const char* kernel, double* total_ms, int64_t* launches) {
+    if (!kernel || !total_ms || !launches) return set_error(KD_EINVAL, "kd_timing_collect: NULL argument");
+    std::vector<TimedLaunch> all;
+    {
+        std::lock_guard<std::mutex> lk(g_timing_mu);
+        all.swap(g_timed);
+    }
+    double ms = 0;
+    int64_t n = 0;
+    kd_status st = KD_OK;
+    for (auto& t : all) {
+        if (st == KD_OK && t.kernel == kernel) {
+            hipError_t e = hipEventSynchronize(t.b);
+            float m = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&m, t.a, t.b);
+            if (e != hipSuccess) st = hip_error(e, "kd_timing_collect");
+            ms += m;
+            ++n;
+        }
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    *total_ms = ms;
+    *launches = n;
+    return st;
+}
+
+const char* kd_version(void) { return "kdtree-gfx950 0.1"; }
+
+}  // extern "C"

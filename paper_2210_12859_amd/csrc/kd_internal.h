@@ -1,0 +1,96 @@
+// kd_internal.h -- internal declarations shared by the libkdtree sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/kdtree.h"
+
+namespace kd {
+
+// Node record in the array-of-structures layout: the D coordinates followed by
+// the caller index, one record per level-order position.  D=3 gives 16 B
+// records (one dwordx4 load per node).
+template <int D>
+struct alignas(D == 3 ? 16 : 4) NodeRec {
+    float c[D];
+    int32_t idx;
+};
+
+// Tuned launch parameters kept with a tree (filled by kd_autotune).
+struct TuneEntry {
+    int k_template;  // compiled list size
+    kd_opts opts;
+};
+
+struct Workspace;
+
+}  // namespace kd
+
+struct kd_tree_s {
+    int64_t N = 0;
+    int dim = 0;
+    int device = 0;
+    float lo[4] = {0, 0, 0, 0};
+    float hi[4] = {0, 0, 0, 0};
+    void* d_nodes = nullptr;       // NodeRec<dim>[N]
+    std::vector<int32_t> order;    // host copy: order[pos] = caller index
+    std::mutex tune_mu;
+    std::vector<kd::TuneEntry> tuned;
+};
+
+namespace kd {
+
+// ---- errors -------------------------------------------------------------
+kd_status set_error(kd_status s, const std::string& msg);
+kd_status hip_error(hipError_t e, const char* what);
+#define KD_HIP(call)                                                \
+    do {                                                            \
+        hipError_t _e = (call);                                     \
+        if (_e != hipSuccess) return ::kd::hip_error(_e, #call);    \
+    } while (0)
+
+// ---- host builder (kd_build_host.cpp) -------------------------------------
+int64_t left_subtree_size(int64_t n);
+// order[pos] = caller index; threads <= 0 picks the hardware count.
+void build_level_order(const float* pts, int64_t N, int dim, int32_t* order, int threads);
+
+// ---- device info --------------------------------------------------------
+struct DeviceInfo {
+    int cus = 256;
+    int lds_bytes = 160 * 1024;
+    int xcds = 8;
+};
+const DeviceInfo& device_info(int device);
+
+// ---- per-stream scratch (kd_api.cpp) --------------------------------------
+// Returns a device buffer of at least `bytes`, private to (device, stream).
+// Calls on one stream are ordered, so reuse across calls is safe.
+kd_status scratch(kd_stream stream, size_t bytes, void** out);
+
+// ---- kernel timing hook (kd_api.cpp) --------------------------------------
+// When enabled, launches of the named kernel are bracketed by hipEvents on
+// the stream they run on; kd_timing_collect sums the elapsed times.
+bool timing_enabled();
+kd_status timing_begin(hipStream_t st, hipEvent_t* ev);
+kd_status timing_end(hipStream_t st, hipEvent_t ev0, const char* kernel);
+
+// ---- query pipeline (kd_traverse.hip) -------------------------------------
+struct QueryPlan {
+    int k = 1;
+    int K = 1;          // compiled list size >= k
+    float R2 = 0;
+    int block = 256;
+    int lds_levels = 10;
+    int sort_bits = 32;
+    int waves_per_cu = 8;
+};
+int k_template(int k);
+kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan,
+                  int32_t* out_idx, float* out_d2, uint32_t* visited, kd_stream stream);
+
+}  // namespace kd
