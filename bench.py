@@ -75,6 +75,18 @@ def cpu_baseline(P, Qs, k, reps=2):
                        f"best of {reps}, tree built untimed")
 
 
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain copy kernel of known size: each launch reads and writes nbytes.
+    rocprofv3 FETCH_SIZE / WRITE_SIZE of this kernel give the counters' scale."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,7 +95,12 @@ def main():
     ap.add_argument("--workload", default="uniform-1m", choices=sorted(WORKLOADS))
     ap.add_argument("--k", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "

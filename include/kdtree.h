@@ -131,7 +131,7 @@ kd_status kd_knn_ex(kd_tree t, const float* queries, int64_t Q, int k, float max
  * traversal kernel ("traverse") and of its other stages is bracketed by
  * hipEvents recorded on the stream it runs on.  kd_timing_collect waits for
  * the recorded events of one kernel name, returns the summed elapsed time in
- * milliseconds and the launch count, and clears all recorded events. */
+ * milliseconds and the launch count, and forgets that kernel's events. */
 kd_status kd_timing_enable(int on);
 kd_status kd_timing_collect(const char* kernel, double* total_ms, int64_t* launches);
 

@@ -27,6 +27,7 @@ SOURCES = [
     ("kd_api.cpp", True),
     ("kd_build_host.cpp", False),
     ("kd_traverse.hip", True),
+    ("kd_sort.hip", True),
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",

@@ -111,12 +111,19 @@ namespace {
 
 template <int D>
 void pack_records(const float* pts, const int32_t* order, int64_t N, std::vector<unsigned char>& out) {
-    out.resize(size_t(N) * sizeof(NodeRec<D>));
-    NodeRec<D>* r = reinterpret_cast<NodeRec<D>*>(out.data());
+    out.assign(size_t(N) * sizeof(TreeRec<D>), 0);
+    TreeRec<D>* r = reinterpret_cast<TreeRec<D>*>(out.data());
     for (int64_t pos = 0; pos < N; ++pos) {
         const int32_t i = order[pos];
         for (int j = 0; j < D; ++j) r[pos].c[j] = pts[int64_t(i) * D + j];
         r[pos].idx = i;
+        // ancestors by 1-based id: a = (pos+1) >> m, level floor(log2 a)
+        int64_t a = (pos + 1) >> 1;
+        for (int m = 0; m < 7 - D; ++m, a >>= 1) {
+            if (a < 1) break;
+            const int lvl = 63 - __builtin_clzll((unsigned long long)a);
+            r[pos].anc[m] = pts[int64_t(order[a - 1]) * D + (lvl % D)];
+        }
     }
 }
 
@@ -197,9 +204,9 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     kd_opts use{0, -1, -1, 0};
     if (o) use = *o;
     if (use.block == 0) use.block = 256;
-    if (use.lds_levels < 0) use.lds_levels = 10;
-    if (use.sort_bits < 0) use.sort_bits = 32;
-    if (use.waves_per_cu == 0) use.waves_per_cu = 8;
+    if (use.lds_levels < 0) use.lds_levels = 0;
+    if (use.sort_bits < 0) use.sort_bits = 16;
+    if (use.waves_per_cu == 0) use.waves_per_cu = 16;
     if (use.block != 64 && use.block != 128 && use.block != 256)
         return set_error(KD_EINVAL, "opts.block must be 64, 128 or 256");
     if (use.lds_levels > 13) return set_error(KD_EINVAL, "opts.lds_levels must be <= 13");
@@ -344,13 +351,15 @@ kd_status kd_timing_collect(const char* kernel, double* total_ms, int64_t* launc
     std::vector<TimedLaunch> all;
     {
         std::lock_guard<std::mutex> lk(g_timing_mu);
-        all.swap(g_timed);
+        std::vector<TimedLaunch> keep;
+        for (auto& t : g_timed) (t.kernel == kernel ? all : keep).push_back(t);
+        g_timed.swap(keep);
     }
     double ms = 0;
     int64_t n = 0;
     kd_status st = KD_OK;
     for (auto& t : all) {
-        if (st == KD_OK && t.kernel == kernel) {
+        if (st == KD_OK) {
             hipError_t e = hipEventSynchronize(t.b);
             float m = 0;
             if (e == hipSuccess) e = hipEventElapsedTime(&m, t.a, t.b);

@@ -13,12 +13,25 @@
 namespace kd {
 
 // Node record in the array-of-structures layout: the D coordinates followed by
-// the caller index, one record per level-order position.  D=3 gives 16 B
-// records (one dwordx4 load per node).
+// the caller index, one record per level-order position, padded to 16 bytes
+// (D = 2, 3) or 32 bytes (D = 4) so that one aligned vector load fetches a
+// whole node.
 template <int D>
-struct alignas(D == 3 ? 16 : 4) NodeRec {
+struct alignas(16) NodeRec {
     float c[D];
     int32_t idx;
+};
+
+// Tree node record, 32 bytes: the D coordinates, the caller index, then the
+// split values of the 7 - D nearest ancestors, parent first (the coordinate of
+// the ancestor's point in that ancestor's split dimension).  The ancestor
+// splits let a lane resolve several consecutive "return to parent" steps of
+// the traversal from the record it already holds, without loading the parents.
+template <int D>
+struct alignas(32) TreeRec {
+    float c[D];
+    int32_t idx;
+    float anc[7 - D];
 };
 
 // Tuned launch parameters kept with a tree (filled by kd_autotune).
@@ -37,7 +50,7 @@ struct kd_tree_s {
     int device = 0;
     float lo[4] = {0, 0, 0, 0};
     float hi[4] = {0, 0, 0, 0};
-    void* d_nodes = nullptr;       // NodeRec<dim>[N]
+    void* d_nodes = nullptr;       // TreeRec<dim>[N], level order
     std::vector<int32_t> order;    // host copy: order[pos] = caller index
     std::mutex tune_mu;
     std::vector<kd::TuneEntry> tuned;
@@ -90,6 +103,10 @@ struct QueryPlan {
     int waves_per_cu = 8;
 };
 int k_template(int k);
+// Morton reorder of query slots (kd_sort.hip)
+size_t sort_scratch_bytes(int64_t Q);
+kd_status morton_sort(kd_tree t, const float* queries, int64_t Q, int sort_bits, void* ws, hipStream_t st,
+                      const uint32_t** perm_out);
 kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan,
                   int32_t* out_idx, float* out_d2, uint32_t* visited, kd_stream stream);
 

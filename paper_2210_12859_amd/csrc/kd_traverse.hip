@@ -8,24 +8,33 @@
 //   * second visit (prev == close child): step to the far child if its
 //     subtree is still in range, else to the parent;
 //   * third visit (prev == far child): step to the parent;
-//   * the root stepping to its parent (-1) ends the traversal.
+//   * the root stepping to its parent ends the traversal.
 // The close child is the right child iff q[dim] - split > 0 (Sec. 3.2).  The
 // far-range test is taken in squared form, fl(sd*sd) <= worst d2 of the list,
 // non-strict: every point of the far subtree has d2 >= fl(sd*sd), so the test
 // never prunes a point that could enter the list, ties included.
 //
-// Visits to children that do not exist (index >= N) are resolved in the same
-// loop trip instead of stepping there and bouncing back: the next node is
-// chosen exactly as the bounce would have chosen it, so the processed-node
-// sequence equals the paper's (and the ordered recursion's).
+// Node ids inside the kernel are 1-based (id = array position + 1): children
+// of i are 2i and 2i+1, the sibling of c is c^1, the parent is i>>1, and the
+// root's parent is 0, which ends the traversal.  This is the paper's
+// level-order layout with the index shifted by one.
+//
+// Several state-machine steps run per loop trip, always in the paper's order:
+//   * a step onto a child that does not exist (id > N) and the bounce back
+//     are resolved in place: the next node is the one the bounce would pick;
+//   * "return to parent" steps are resolved with the ancestor split values
+//     stored in the current node's record (up to three levels), so a lane
+//     does not reload its parents to learn which child it came from.
+// The processed-node sequence therefore equals the paper's, and the ordered
+// recursion's, node for node.
 //
 // MI355X mapping
-//   * persistent grid; each wave pulls chunks of 64 sorted query slots from
-//     a global counter; lanes whose query finished are refilled under one
-//     wave-uniform branch (ballot + mbcnt), so waves stay full;
-//   * the top tree levels are staged in LDS once per workgroup;
-//   * nodes are 16-byte records (x, y, z, caller index) for D=3: one dwordx4
-//     load per loop trip gives the split coordinate, the point and its index;
+//   * persistent grid; XCD x serves the x-th eighth of the Morton-sorted
+//     queries (its L2 holds that region of the tree), stealing at the end;
+//   * each wave pulls 64 queries at a time with one coalesced load and hands
+//     them to idle lanes by cross-lane shuffle, so a lane restarts without a
+//     memory round trip;
+//   * nodes are 32-byte records loaded as two dwordx4 from one cache line;
 //   * the k-best list lives in VGPRs as 64-bit keys (d2 bits << 32 | index),
 //     so the lexicographic (d2, index) order is one unsigned compare (d2 >= 0,
 //     and the bit pattern of a non-negative float is monotone); insertion is
@@ -41,18 +50,17 @@ namespace {
 constexpr uint32_t SENT_IDX = 0x7fffffffu;
 
 struct TravArgs {
-    const void* nodes;       // NodeRec<D>[N]
+    const void* nodes;       // TreeRec<D>[N], level order
     int32_t N;
-    int32_t lds_nodes;       // records staged in LDS (a prefix of the array)
-    const float* queries;    // caller [Q][D]
-    const int32_t* perm;     // slot -> caller row; NULL = identity
+    const void* sq;          // NodeRec<D>[Q]: queries in traversal order, .idx = caller row
     uint32_t Q;              // query slots
     int k;                   // requested k (<= K)
     float R2;                // fl32(maxRadius^2)
     int32_t* out_idx;        // [Q][k] caller order
     float* out_d2;           // [Q][k] or NULL
     uint32_t* visited;       // [Q] or NULL
-    uint32_t* counter;       // work-queue cursor, zero at launch
+    uint32_t* counter;       // [8] per-XCD work cursors, zero at launch
+    int vec_store;           // outputs 16-byte aligned with k % 4 == 0: vector stores
 };
 
 __device__ __forceinline__ uint64_t make_key(float d2, int32_t idx) {
@@ -74,161 +82,305 @@ __device__ __forceinline__ void list_insert(uint64_t (&L)[K], uint64_t key) {
 }
 
 template <int D>
-__device__ __forceinline__ NodeRec<D> load_node(const NodeRec<D>* __restrict__ g, const NodeRec<D>* l,
-                                                int32_t curr, int32_t lds_nodes) {
+__device__ __forceinline__ int dim_up(int d) { return d == 0 ? D - 1 : d - 1; }
+template <int D>
+__device__ __forceinline__ int dim_down(int d) { return d == D - 1 ? 0 : d + 1; }
+
+// v[(dim - i) mod D]; the compares against constants are shared across calls.
+// (I is a constant after unrolling, so the compares are against constants.)
+template <int D>
+__device__ __forceinline__ float sel_rot(const float (&v)[D], int dim, int I) {
+    float r = v[(D - I % D) % D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const int want = (j + I) % D;  // dim value for which v[j] is picked
+        if (want != 0) r = (dim == want) ? v[j] : r;
+    }
+    return r;
+}
+
+// Whole-record loads (two dwordx4 from one 32-byte aligned record).
+template <int D>
+__device__ __forceinline__ void load_tree(const TreeRec<D>* p, float (&c)[D], int32_t& idx, float (&anc)[7 - D]) {
+    const uint4 lo = reinterpret_cast<const uint4*>(p)[0];
+    const uint4 hi = reinterpret_cast<const uint4*>(p)[1];
+    const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = __uint_as_float(w[j]);
+    idx = int32_t(w[D]);
+#pragma unroll
+    for (int j = 0; j < 7 - D; ++j) anc[j] = __uint_as_float(w[D + 1 + j]);
+}
+
+// Query records (16 bytes for D <= 3, 32 for D = 4).
+template <int D>
+__device__ __forceinline__ NodeRec<D> load_query(const NodeRec<D>* p) {
+    const uint4 lo = reinterpret_cast<const uint4*>(p)[0];
     NodeRec<D> r;
-    if (curr < lds_nodes) {
-        r = l[curr];
+    const uint32_t w[4] = {lo.x, lo.y, lo.z, lo.w};
+    if (D < 4) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) r.c[j] = __uint_as_float(w[j]);
+        r.idx = int32_t(w[D < 4 ? D : 0]);
     } else {
-        r = g[curr];
+#pragma unroll
+        for (int j = 0; j < D; ++j) r.c[j] = __uint_as_float(w[j]);
+        r.idx = int32_t(reinterpret_cast<const uint4*>(p)[1].x);
     }
     return r;
 }
 
 template <int D>
-__device__ __forceinline__ int dim_step(int dim, bool down) {
-    int d = dim + (down ? 1 : D - 1);
-    return d >= D ? d - D : d;
+__device__ __forceinline__ NodeRec<D> shfl_rec(const NodeRec<D>& r, int src) {
+    NodeRec<D> o;
+#pragma unroll
+    for (int j = 0; j < D; ++j) o.c[j] = __shfl(r.c[j], src);
+    o.idx = __shfl(r.idx, src);
+    return o;
 }
 
-// Per-lane query state.
+// Per-lane query state: the two node ids of the state machine (1-based),
+// the split dimension of `curr` (implied by its level, tracked as the lane
+// moves), the query and its k-best list.
 template <int D, int K>
 struct Lane {
     float q[D];
     uint64_t L[K];
     int32_t curr, prev;
     int dim;
-    uint32_t slot;
+    int32_t row;
     uint32_t vis;
 };
 
 template <int D, int K>
-__device__ __forceinline__ void lane_start(Lane<D, K>& s, const TravArgs& a, uint32_t slot) {
-    s.slot = slot;
-    const int32_t row = a.perm ? a.perm[slot] : int32_t(slot);
+__device__ __forceinline__ void lane_start(Lane<D, K>& s, const TravArgs& a, const NodeRec<D>& qr) {
 #pragma unroll
-    for (int j = 0; j < D; ++j) s.q[j] = a.queries[int64_t(row) * D + j];
+    for (int j = 0; j < D; ++j) s.q[j] = qr.c[j];
+    s.row = qr.idx;
     // Slots beyond k hold the smallest key so the list's worst entry is the
     // k-th real one; real keys are >= 0 and never move in front of them.
     const uint64_t sent = make_key(a.R2, SENT_IDX);
 #pragma unroll
     for (int j = 0; j < K; ++j) s.L[j] = (j < K - a.k) ? uint64_t(0) : sent;
-    s.curr = 0;
-    s.prev = -1;
+    s.curr = 1;   // root
+    s.prev = 0;   // the root's parent
     s.dim = 0;
     s.vis = 0;
 }
 
-template <int D, int K, bool COUNT>
+template <int D, int K>
 __device__ __forceinline__ void lane_finish(const Lane<D, K>& s, const TravArgs& a) {
-    const int32_t row = a.perm ? a.perm[s.slot] : int32_t(s.slot);
-    int32_t* oi = a.out_idx + int64_t(row) * a.k;
-    float* od = a.out_d2 ? a.out_d2 + int64_t(row) * a.k : nullptr;
+    int32_t* oi = a.out_idx + int64_t(s.row) * a.k;
+    float* od = a.out_d2 ? a.out_d2 + int64_t(s.row) * a.k : nullptr;
     const int off = K - a.k;
+    if (K >= 4 && a.vec_store) {
+        // rows are 16-byte aligned: vector stores
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        if (j >= off) {
-            const uint32_t id = uint32_t(s.L[j]);
-            const bool empty = id == SENT_IDX;
-            oi[j - off] = empty ? -1 : int32_t(id);
-            if (od) od[j - off] = empty ? __builtin_inff() : key_d2(s.L[j]);
+        for (int j = 0; j < K; j += 4) {
+            if (j >= off) {
+                int4 vi;
+                vi.x = int32_t(uint32_t(s.L[j + 0]));
+                vi.y = int32_t(uint32_t(s.L[j + 1]));
+                vi.z = int32_t(uint32_t(s.L[j + 2]));
+                vi.w = int32_t(uint32_t(s.L[j + 3]));
+                float4 vd = make_float4(key_d2(s.L[j]), key_d2(s.L[j + 1]), key_d2(s.L[j + 2]), key_d2(s.L[j + 3]));
+                if (vi.x == int32_t(SENT_IDX)) { vi.x = -1; vd.x = __builtin_inff(); }
+                if (vi.y == int32_t(SENT_IDX)) { vi.y = -1; vd.y = __builtin_inff(); }
+                if (vi.z == int32_t(SENT_IDX)) { vi.z = -1; vd.z = __builtin_inff(); }
+                if (vi.w == int32_t(SENT_IDX)) { vi.w = -1; vd.w = __builtin_inff(); }
+                *reinterpret_cast<int4*>(oi + (j - off)) = vi;
+                if (od) *reinterpret_cast<float4*>(od + (j - off)) = vd;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (j >= off) {
+                const uint32_t id = uint32_t(s.L[j]);
+                const bool empty = id == SENT_IDX;
+                oi[j - off] = empty ? -1 : int32_t(id);
+                if (od) od[j - off] = empty ? __builtin_inff() : key_d2(s.L[j]);
+            }
         }
     }
-    if (COUNT && a.visited) a.visited[row] = s.vis;
+    if (a.visited) a.visited[s.row] = s.vis;
 }
 
-// One trip of the state machine.  Returns the next node (-1 = finished).
-template <int D, int K, bool COUNT>
-__device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const NodeRec<D>* __restrict__ g,
-                                             const NodeRec<D>* l, int32_t N, int32_t lds_nodes) {
+// One loop trip for a lane at node s.curr (record fields c, idx, anc):
+// the state-machine step at curr, then up to F fused "return to parent"
+// steps.  Returns the new curr (0 = traversal finished).
+template <int D, int K, int F>
+__device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D], int32_t idx,
+                                             const float (&anc)[7 - D], int32_t N) {
     const int32_t curr = s.curr;
-    const NodeRec<D> r = load_node<D>(g, l, curr, lds_nodes);
+    const int dim = (31 - __clz(curr)) % D;  // level of curr, mod D
     float dx[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) dx[j] = s.q[j] - r.c[j];
-    float sd = dx[0];
-#pragma unroll
-    for (int j = 1; j < D; ++j) sd = (s.dim == j) ? dx[j] : sd;
+    for (int j = 0; j < D; ++j) dx[j] = s.q[j] - c[j];
+    const float sd = sel_rot<D>(dx, dim, 0);
 
     const bool from_parent = s.prev < curr;
-    if (from_parent) {
-        // processNode: exact binary32 squared distance, left to right.
-        float d2 = dx[0] * dx[0];
+    // processNode on the first visit: exact binary32 squared distance, left
+    // to right (computed branch-free; only the insertion is conditional).
+    float d2 = dx[0] * dx[0];
 #pragma unroll
-        for (int j = 1; j < D; ++j) d2 = d2 + dx[j] * dx[j];
-        const uint64_t key = make_key(d2, r.idx);
-        if (COUNT) s.vis++;
-        if (key < s.L[K - 1]) list_insert<K>(s.L, key);
-    }
+    for (int j = 1; j < D; ++j) d2 = d2 + dx[j] * dx[j];
+    const uint64_t key = make_key(d2, idx);
+    s.vis += from_parent ? 1u : 0u;
+    if (from_parent && key < s.L[K - 1]) list_insert<K>(s.L, key);
+
     const float worst = key_d2(s.L[K - 1]);
     const bool far_in = sd * sd <= worst;
-    const int32_t close_side = sd > 0.0f ? 1 : 0;
-    const int32_t close_c = 2 * curr + 1 + close_side;
-    const int32_t far_c = 2 * curr + 2 - close_side;
-    const int32_t parent = (curr - 1) >> 1;  // -1 for the root
-    const bool close_ok = close_c < N;
-    const bool try_far = from_parent ? !close_ok : (s.prev == close_c);
-    const bool go_close = from_parent && close_ok;
-    const bool go_far = try_far && far_in && far_c < N;
-    const int32_t next = go_close ? close_c : (go_far ? far_c : parent);
-    s.dim = dim_step<D>(s.dim, go_close || go_far);
-    s.prev = curr;
+    const int32_t close_c = (curr << 1) | (sd > 0.0f ? 1 : 0);
+    const int32_t far_c = close_c ^ 1;
+    const bool close_ok = close_c <= N;
+    const bool go_close = from_parent & close_ok;
+    const bool try_far = (from_parent & !close_ok) | (!from_parent & (s.prev == close_c));
+    const bool go_far = try_far & far_in & (far_c <= N);
+    bool up = !(go_close | go_far);
+    int32_t child = curr;        // node being returned from
+    int32_t anc_id = curr >> 1;  // node being returned to
+    int32_t next = go_close ? close_c : far_c;
+    int32_t nprev = curr;
+
+    // Fused returns.  At ancestor anc_id (depth i above curr: split anc[i],
+    // dimension dim-1-i): the lane came from `child`; if that is the close
+    // child and the far subtree is in range, step to the far child, else
+    // keep returning.
+#pragma unroll
+    for (int i = 0; i < F; ++i) {
+        const bool live = up & (anc_id != 0);
+        if (__any(live)) {
+            if (live) {
+                const float sda = sel_rot<D>(s.q, dim, i + 1) - anc[i];
+                const bool child_is_close = (child & 1) == (sda > 0.0f ? 1 : 0);
+                const int32_t fa = child ^ 1;
+                const bool take_far = child_is_close & (sda * sda <= worst) & (fa <= N);
+                if (take_far) {
+                    next = fa;
+                    nprev = anc_id;
+                    up = false;
+                } else {
+                    child = anc_id;
+                    anc_id >>= 1;
+                }
+            }
+        }
+    }
+    if (up) {
+        next = anc_id;  // 0 once the root has returned: finished
+        nprev = child;
+    }
+    s.prev = nprev;
     s.curr = next;
     return next;
 }
 
-template <int D, int K, bool COUNT>
+// Wave-uniform work source: XCD x owns the sorted slots [x*Q/8, (x+1)*Q/8),
+// so the queries one XCD serves are spatially close and its L2 holds their
+// part of the tree; a wave whose range is used up steals from the next XCDs.
+struct WorkSource {
+    uint32_t xcd;
+    uint32_t src;       // 0..8: ranges tried so far
+    bool exhausted;
+
+    __device__ __forceinline__ void grab(const TravArgs& a, uint32_t lane, uint32_t& cb, uint32_t& cn) {
+        cb = 0;
+        cn = 0;
+        while (src < 8) {
+            const uint32_t x = (xcd + src) & 7u;
+            const uint32_t beg = uint32_t((uint64_t(x) * a.Q) >> 3);
+            const uint32_t end = uint32_t((uint64_t(x + 1) * a.Q) >> 3);
+            uint32_t c = 0;
+            if (lane == 0) c = atomicAdd(&a.counter[x], 64u);
+            c = __builtin_amdgcn_readfirstlane(c);
+            if (c < end - beg) {
+                cb = beg + c;
+                cn = end - cb < 64u ? end - cb : 64u;
+                return;
+            }
+            ++src;
+        }
+        exhausted = true;
+    }
+};
+
+template <int D, int K, int F>
 __global__ __launch_bounds__(256) void knn_persistent(TravArgs a) {
-    extern __shared__ unsigned char smem_raw[];
-    NodeRec<D>* lnodes = reinterpret_cast<NodeRec<D>*>(smem_raw);
-    const NodeRec<D>* __restrict__ g = reinterpret_cast<const NodeRec<D>*>(a.nodes);
-    for (int i = threadIdx.x; i < a.lds_nodes; i += blockDim.x) lnodes[i] = g[i];
-    __syncthreads();
+    const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes) - 1;  // 1-based
+    const NodeRec<D>* __restrict__ sq = reinterpret_cast<const NodeRec<D>*>(a.sq);
 
     const uint32_t lane = __lane_id();
-    // wave-private reservoir of query slots [rbase, rbase + rleft)
-    uint32_t rbase = 0, rleft = 0;
-    if (lane == 0) rbase = atomicAdd(a.counter, 64u);
-    rbase = __builtin_amdgcn_readfirstlane(rbase);
-    rleft = 64;
+    const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
+    WorkSource ws{blockIdx.x & 7u, 0u, false};
+    // Query chunk held across the wave: lane l holds slot cb + l of the
+    // current chunk; idle lanes take queries from it by cross-lane shuffle.
+    NodeRec<D> chunk;
+    uint32_t cpos = 0, cn = 0;
 
     Lane<D, K> s;
-    bool active = rbase + lane < a.Q;
-    if (active) lane_start<D, K>(s, a, rbase + lane);
-    rbase += 64;
-    rleft = 0;
-
-    while (__builtin_amdgcn_read_exec() != 0 && __any(active)) {
-        bool done = false;
-        if (active) {
-            const int32_t next = lane_step<D, K, COUNT>(s, g, lnodes, a.N, a.lds_nodes);
-            done = next < 0;
+    bool active = false;
+    for (;;) {
+        const uint64_t need = __ballot(!active);
+        if (need && !ws.exhausted) {
+            const uint32_t n = __popcll(need);
+            const uint32_t rank = __popcll(need & lt_mask);
+            const uint32_t take1 = n < cn - cpos ? n : cn - cpos;
+            {
+                const NodeRec<D> v = shfl_rec<D>(chunk, int(cpos + (rank < take1 ? rank : 0)));
+                if (!active && rank < take1) {
+                    lane_start<D, K>(s, a, v);
+                    active = true;
+                }
+            }
+            cpos += take1;
+            if (n > take1) {
+                uint32_t cb = 0, cn2 = 0;
+                ws.grab(a, lane, cb, cn2);
+                if (cn2) {
+                    if (lane < cn2) chunk = load_query<D>(sq + cb + lane);
+                    cn = cn2;
+                    const uint32_t r2 = rank - take1;
+                    const uint32_t take2 = n - take1 < cn2 ? n - take1 : cn2;
+                    const NodeRec<D> v = shfl_rec<D>(chunk, int(r2 < take2 ? r2 : 0));
+                    if (!active && rank >= take1 && r2 < take2) {
+                        lane_start<D, K>(s, a, v);
+                        active = true;
+                    }
+                    cpos = take2;
+                } else {
+                    cn = 0;
+                    cpos = 0;
+                }
+            }
         }
-        const uint64_t dmask = __ballot(done);
-        if (dmask) {
-            if (done) lane_finish<D, K, COUNT>(s, a);
-            const uint32_t n = __popcll(dmask);
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(uint32_t(dmask >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo(uint32_t(dmask), 0u));
-            uint32_t nb = 0;
-            if (rleft < n) {
-                if (lane == 0) nb = atomicAdd(a.counter, 64u);
-                nb = __builtin_amdgcn_readfirstlane(nb);
-            }
-            if (done) {
-                const uint32_t slot = rank < rleft ? rbase + rank : nb + (rank - rleft);
-                active = slot < a.Q;
-                if (active) lane_start<D, K>(s, a, slot);
-            }
-            if (rleft < n) {
-                rbase = nb + (n - rleft);
-                rleft = 64 - (n - rleft);
-            } else {
-                rbase += n;
-                rleft -= n;
+        if (!__any(active)) break;
+        if (active) {
+            float c[D];
+            int32_t idx;
+            float anc[7 - D];
+            load_tree<D>(g1 + s.curr, c, idx, anc);
+            const int32_t next = lane_step<D, K, F>(s, c, idx, anc, a.N);
+            if (next == 0) {
+                lane_finish<D, K>(s, a);
+                active = false;
             }
         }
     }
+}
+
+// sq[slot] = (queries[row], row), row = perm[slot] (identity when perm is NULL)
+template <int D>
+__global__ void gather_queries(const float* __restrict__ queries, const uint32_t* __restrict__ perm, uint32_t Q,
+                               NodeRec<D>* __restrict__ sq) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Q) return;
+    const uint32_t row = perm ? perm[i] : i;
+    NodeRec<D> r;
+#pragma unroll
+    for (int j = 0; j < D; ++j) r.c[j] = queries[size_t(row) * D + j];
+    r.idx = int32_t(row);
+    sq[i] = r;
 }
 
 __global__ void zero_u32(uint32_t* p, int n) {
@@ -236,32 +388,36 @@ __global__ void zero_u32(uint32_t* p, int n) {
     if (i < n) p[i] = 0;
 }
 
-template <int D, int K, bool COUNT>
-hipError_t launch_knn(const TravArgs& a, int block, int grid, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL((knn_persistent<D, K, COUNT>), dim3(grid), dim3(block), lds_bytes, st, a);
+#ifndef KD_FUSED_LEVELS
+#define KD_FUSED_LEVELS 3
+#endif
+constexpr int fused_levels(int D) { return KD_FUSED_LEVELS < 7 - D ? KD_FUSED_LEVELS : 7 - D; }
+
+template <int D, int K>
+hipError_t launch_knn(const TravArgs& a, int block, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((knn_persistent<D, K, fused_levels(D)>), dim3(grid), dim3(block), 0, st, a);
     return hipGetLastError();
 }
 
-template <int D, bool COUNT>
-hipError_t dispatch_k(int K, const TravArgs& a, int block, int grid, size_t lds, hipStream_t st) {
+template <int D>
+hipError_t dispatch_k(int K, const TravArgs& a, int block, int grid, hipStream_t st) {
     switch (K) {
-        case 1: return launch_knn<D, 1, COUNT>(a, block, grid, lds, st);
-        case 2: return launch_knn<D, 2, COUNT>(a, block, grid, lds, st);
-        case 4: return launch_knn<D, 4, COUNT>(a, block, grid, lds, st);
-        case 8: return launch_knn<D, 8, COUNT>(a, block, grid, lds, st);
-        case 16: return launch_knn<D, 16, COUNT>(a, block, grid, lds, st);
-        case 32: return launch_knn<D, 32, COUNT>(a, block, grid, lds, st);
-        case 64: return launch_knn<D, 64, COUNT>(a, block, grid, lds, st);
+        case 1: return launch_knn<D, 1>(a, block, grid, st);
+        case 2: return launch_knn<D, 2>(a, block, grid, st);
+        case 4: return launch_knn<D, 4>(a, block, grid, st);
+        case 8: return launch_knn<D, 8>(a, block, grid, st);
+        case 16: return launch_knn<D, 16>(a, block, grid, st);
+        case 32: return launch_knn<D, 32>(a, block, grid, st);
+        case 64: return launch_knn<D, 64>(a, block, grid, st);
     }
     return hipErrorInvalidValue;
 }
 
-template <bool COUNT>
-hipError_t dispatch_dk(int D, int K, const TravArgs& a, int block, int grid, size_t lds, hipStream_t st) {
+hipError_t dispatch_dk(int D, int K, const TravArgs& a, int block, int grid, hipStream_t st) {
     switch (D) {
-        case 2: return dispatch_k<2, COUNT>(K, a, block, grid, lds, st);
-        case 3: return dispatch_k<3, COUNT>(K, a, block, grid, lds, st);
-        case 4: return dispatch_k<4, COUNT>(K, a, block, grid, lds, st);
+        case 2: return dispatch_k<2>(K, a, block, grid, st);
+        case 3: return dispatch_k<3>(K, a, block, grid, st);
+        case 4: return dispatch_k<4>(K, a, block, grid, st);
     }
     return hipErrorInvalidValue;
 }
@@ -272,6 +428,16 @@ size_t rec_bytes(int D) {
         case 3: return sizeof(NodeRec<3>);
         default: return sizeof(NodeRec<4>);
     }
+}
+
+hipError_t launch_gather(int D, const float* queries, const uint32_t* perm, uint32_t Q, void* sq, hipStream_t st) {
+    const dim3 grid((Q + 255) / 256), block(256);
+    switch (D) {
+        case 2: hipLaunchKernelGGL(gather_queries<2>, grid, block, 0, st, queries, perm, Q, (NodeRec<2>*)sq); break;
+        case 3: hipLaunchKernelGGL(gather_queries<3>, grid, block, 0, st, queries, perm, Q, (NodeRec<3>*)sq); break;
+        default: hipLaunchKernelGGL(gather_queries<4>, grid, block, 0, st, queries, perm, Q, (NodeRec<4>*)sq); break;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -287,22 +453,33 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const DeviceInfo& dev = device_info(t->device);
     void* ws = nullptr;
-    kd_status s = scratch(stream, 256, &ws);
+    const size_t head = 256;
+    const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
+    const size_t sort_bytes = plan.sort_bits > 0 ? sort_scratch_bytes(Q) : 0;
+    kd_status s = scratch(stream, head + sq_bytes + sort_bytes, &ws);
     if (s != KD_OK) return s;
     uint32_t* counter = reinterpret_cast<uint32_t*>(ws);
-    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, counter, 1);
+    void* sq = static_cast<char*>(ws) + head;
+    void* sort_ws = static_cast<char*>(ws) + head + sq_bytes;
+    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, counter, 8);
     KD_HIP(hipGetLastError());
+
+    // query reorder: Morton sort, then gather into traversal order
+    const uint32_t* perm = nullptr;
+    hipEvent_t evs;
+    s = timing_begin(st, &evs);
+    if (s != KD_OK) return s;
+    s = morton_sort(t, queries, Q, plan.sort_bits, sort_ws, st, &perm);
+    if (s != KD_OK) return s;
+    hipError_t e = launch_gather(t->dim, queries, perm, uint32_t(Q), sq, st);
+    if (e != hipSuccess) return hip_error(e, "gather_queries launch");
+    s = timing_end(st, evs, "sort");
+    if (s != KD_OK) return s;
 
     TravArgs a;
     a.nodes = t->d_nodes;
     a.N = int32_t(t->N);
-    int64_t lds_nodes = (int64_t(1) << plan.lds_levels) - 1;
-    if (lds_nodes > t->N) lds_nodes = t->N;
-    size_t lds_bytes = size_t(lds_nodes) * rec_bytes(t->dim);
-    if (lds_bytes > size_t(dev.lds_bytes)) return set_error(KD_EINVAL, "lds_levels too large for LDS");
-    a.lds_nodes = int32_t(lds_nodes);
-    a.queries = queries;
-    a.perm = nullptr;
+    a.sq = sq;
     a.Q = uint32_t(Q);
     a.k = plan.k;
     a.R2 = plan.R2;
@@ -310,18 +487,19 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     a.out_d2 = out_d2;
     a.visited = visited;
     a.counter = counter;
+    a.vec_store = (plan.k % 4 == 0) && (reinterpret_cast<uintptr_t>(out_idx) % 16 == 0) &&
+                  (reinterpret_cast<uintptr_t>(out_d2) % 16 == 0);
 
     const int block = plan.block;
     const int waves_per_block = block / 64;
     int64_t grid = int64_t(dev.cus) * plan.waves_per_cu / waves_per_block;
     const int64_t need = (Q + block - 1) / block;
-    if (grid > need) grid = need;
+    if (grid > need) grid = ((need + 7) / 8) * 8;  // keep every XCD served
     if (grid < 1) grid = 1;
     hipEvent_t ev0;
     s = timing_begin(st, &ev0);
     if (s != KD_OK) return s;
-    hipError_t e = visited ? dispatch_dk<true>(t->dim, plan.K, a, block, int(grid), lds_bytes, st)
-                           : dispatch_dk<false>(t->dim, plan.K, a, block, int(grid), lds_bytes, st);
+    e = dispatch_dk(t->dim, plan.K, a, block, int(grid), st);
     if (e != hipSuccess) return hip_error(e, "knn_persistent launch");
     return timing_end(st, ev0, "traverse");
 }
