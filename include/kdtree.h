@@ -62,11 +62,11 @@ typedef enum {
  * differs.  A zero-initialised struct, or NULL, means "tuned defaults"
  * (the autotuner's cached choice for the tree when kd_autotune ran). */
 typedef struct {
-    int block;       /* threads per workgroup: 64, 128 or 256; 0 = default */
+    int block;       /* threads per workgroup: 64, 128, 256, 512 or 1024 (k > 16: at most 256); 0 = default */
     int lds_levels;  /* top tree levels staged in LDS, 0..12; -1 = default */
     int sort_bits;   /* Morton bits the queries are sorted on before traversal:
                         0 (no reordering), 8, 16, 24 or 32 (all bits); -1 = default */
-    int waves_per_cu;/* persistent grid size in waves per compute unit; 0 = default */
+    int waves_per_cu;/* persistent grid size in waves per compute unit (capped by occupancy); 0 = default */
 } kd_opts;
 
 /* ------------------------------------------------------------ tree build */

@@ -206,9 +206,9 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     if (use.block == 0) use.block = 256;
     if (use.lds_levels < 0) use.lds_levels = 0;
     if (use.sort_bits < 0) use.sort_bits = 16;
-    if (use.waves_per_cu == 0) use.waves_per_cu = 16;
-    if (use.block != 64 && use.block != 128 && use.block != 256)
-        return set_error(KD_EINVAL, "opts.block must be 64, 128 or 256");
+    if (use.waves_per_cu == 0) use.waves_per_cu = 24;
+    if (use.block != 64 && use.block != 128 && use.block != 256 && use.block != 512 && use.block != 1024)
+        return set_error(KD_EINVAL, "opts.block must be 64, 128, 256, 512 or 1024");
     if (use.lds_levels > 13) return set_error(KD_EINVAL, "opts.lds_levels must be <= 13");
     if (use.sort_bits != 0 && use.sort_bits != 8 && use.sort_bits != 16 && use.sort_bits != 24 &&
         use.sort_bits != 32)

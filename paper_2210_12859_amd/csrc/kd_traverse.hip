@@ -29,8 +29,10 @@
 // recursion's, node for node.
 //
 // MI355X mapping
-//   * persistent grid; XCD x serves the x-th eighth of the Morton-sorted
-//     queries (its L2 holds that region of the tree), stealing at the end;
+//   * persistent grid sized to one round of resident workgroups; each
+//     workgroup owns a contiguous range of the Morton-sorted queries (its
+//     CU's L1 and its XCD's L2 hold that region of the tree), with bounded
+//     stealing at the end;
 //   * each wave pulls 64 queries at a time with one coalesced load and hands
 //     them to idle lanes by cross-lane shuffle, so a lane restarts without a
 //     memory round trip;
@@ -59,7 +61,7 @@ struct TravArgs {
     int32_t* out_idx;        // [Q][k] caller order
     float* out_d2;           // [Q][k] or NULL
     uint32_t* visited;       // [Q] or NULL
-    uint32_t* counter;       // [8] per-XCD work cursors, zero at launch
+    uint32_t* counter;       // [gridDim.x] per-workgroup range cursors, zero at launch
     int vec_store;           // outputs 16-byte aligned with k % 4 == 0: vector stores
 };
 
@@ -276,43 +278,67 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     return next;
 }
 
-// Wave-uniform work source: XCD x owns the sorted slots [x*Q/8, (x+1)*Q/8),
-// so the queries one XCD serves are spatially close and its L2 holds their
-// part of the tree; a wave whose range is used up steals from the next XCDs.
+// Wave-uniform work source.  The Morton-sorted slots are cut into one
+// contiguous range per workgroup, so all waves of a workgroup (one CU)
+// traverse the same region of the tree and share its L1 working set.
+// Workgroups on one XCD (blockIdx % 8) get neighbouring ranges, so the XCD's
+// L2 holds one region too.  A wave takes chunks of its group's range until it
+// is used up -- chunks shrink as the range drains -- then steals from up to
+// STEAL_PROBES following ranges.  Stealing is only a speed-up: every range is
+// drained by its own group's waves, so no slot is ever left behind.
+constexpr uint32_t STEAL_PROBES = 32;
+
 struct WorkSource {
-    uint32_t xcd;
-    uint32_t src;       // 0..8: ranges tried so far
+    uint32_t r0;        // own range
+    uint32_t G;         // number of ranges (= workgroups)
+    uint32_t src;       // ranges tried so far
+    uint32_t want;      // next chunk size, 1..64
+    uint32_t wpg;       // waves per workgroup
     bool exhausted;
 
     __device__ __forceinline__ void grab(const TravArgs& a, uint32_t lane, uint32_t& cb, uint32_t& cn) {
         cb = 0;
         cn = 0;
-        while (src < 8) {
-            const uint32_t x = (xcd + src) & 7u;
-            const uint32_t beg = uint32_t((uint64_t(x) * a.Q) >> 3);
-            const uint32_t end = uint32_t((uint64_t(x + 1) * a.Q) >> 3);
+        const uint32_t limit = G < STEAL_PROBES + 1 ? G : STEAL_PROBES + 1;
+        while (src < limit) {
+            uint32_t r = r0 + src;
+            if (r >= G) r -= G;
+            const uint32_t beg = uint32_t((uint64_t(r) * a.Q) / G);
+            const uint32_t end = uint32_t((uint64_t(r + 1) * a.Q) / G);
             uint32_t c = 0;
-            if (lane == 0) c = atomicAdd(&a.counter[x], 64u);
+            if (lane == 0) c = atomicAdd(&a.counter[r], want);
             c = __builtin_amdgcn_readfirstlane(c);
             if (c < end - beg) {
                 cb = beg + c;
-                cn = end - cb < 64u ? end - cb : 64u;
+                cn = end - cb < want ? end - cb : want;
+                const uint32_t rem = end - cb - cn;
+                const uint32_t w = rem / (2 * wpg);
+                want = w < 1 ? 1 : (w > 64 ? 64 : w);
                 return;
             }
             ++src;
+            want = 16;
         }
         exhausted = true;
     }
 };
 
+// Range of workgroup g: groups of one XCD (g % 8) get consecutive ranges.
+__device__ __forceinline__ uint32_t group_range(uint32_t g, uint32_t G) {
+    if (G % 8 != 0) return g;
+    return (g & 7u) * (G >> 3) + (g >> 3);
+}
+
+constexpr int max_block(int K) { return K >= 32 ? 256 : 1024; }
+
 template <int D, int K, int F>
-__global__ __launch_bounds__(256) void knn_persistent(TravArgs a) {
+__global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
     const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes) - 1;  // 1-based
     const NodeRec<D>* __restrict__ sq = reinterpret_cast<const NodeRec<D>*>(a.sq);
 
     const uint32_t lane = __lane_id();
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
-    WorkSource ws{blockIdx.x & 7u, 0u, false};
+    WorkSource ws{group_range(blockIdx.x, gridDim.x), gridDim.x, 0u, 64u, blockDim.x >> 6, false};
     // Query chunk held across the wave: lane l holds slot cb + l of the
     // current chunk; idle lanes take queries from it by cross-lane shuffle.
     NodeRec<D> chunk;
@@ -389,7 +415,7 @@ __global__ void zero_u32(uint32_t* p, int n) {
 }
 
 #ifndef KD_FUSED_LEVELS
-#define KD_FUSED_LEVELS 3
+#define KD_FUSED_LEVELS 1
 #endif
 constexpr int fused_levels(int D) { return KD_FUSED_LEVELS < 7 - D ? KD_FUSED_LEVELS : 7 - D; }
 
@@ -409,6 +435,25 @@ hipError_t dispatch_k(int K, const TravArgs& a, int block, int grid, hipStream_t
         case 16: return launch_knn<D, 16>(a, block, grid, st);
         case 32: return launch_knn<D, 32>(a, block, grid, st);
         case 64: return launch_knn<D, 64>(a, block, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int D>
+hipError_t occupancy_k(int K, int block, int* occ) {
+    switch (K) {
+#define KD_OCC(KK) case KK: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, knn_persistent<D, KK, fused_levels(D)>, block, 0);
+        KD_OCC(1) KD_OCC(2) KD_OCC(4) KD_OCC(8) KD_OCC(16) KD_OCC(32) KD_OCC(64)
+#undef KD_OCC
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t occupancy(int D, int K, int block, int* occ) {
+    switch (D) {
+        case 2: return occupancy_k<2>(K, block, occ);
+        case 3: return occupancy_k<3>(K, block, occ);
+        case 4: return occupancy_k<4>(K, block, occ);
     }
     return hipErrorInvalidValue;
 }
@@ -453,7 +498,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const DeviceInfo& dev = device_info(t->device);
     void* ws = nullptr;
-    const size_t head = 256;
+    const size_t head = 64 * 1024;  // range cursors
     const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
     const size_t sort_bytes = plan.sort_bits > 0 ? sort_scratch_bytes(Q) : 0;
     kd_status s = scratch(stream, head + sq_bytes + sort_bytes, &ws);
@@ -461,8 +506,6 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     uint32_t* counter = reinterpret_cast<uint32_t*>(ws);
     void* sq = static_cast<char*>(ws) + head;
     void* sort_ws = static_cast<char*>(ws) + head + sq_bytes;
-    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, counter, 8);
-    KD_HIP(hipGetLastError());
 
     // query reorder: Morton sort, then gather into traversal order
     const uint32_t* perm = nullptr;
@@ -490,12 +533,22 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     a.vec_store = (plan.k % 4 == 0) && (reinterpret_cast<uintptr_t>(out_idx) % 16 == 0) &&
                   (reinterpret_cast<uintptr_t>(out_d2) % 16 == 0);
 
-    const int block = plan.block;
+    int block = plan.block;
+    if (plan.K >= 32 && block > 256) block = 256;
     const int waves_per_block = block / 64;
-    int64_t grid = int64_t(dev.cus) * plan.waves_per_cu / waves_per_block;
+    int occ = 0;
+    e = occupancy(t->dim, plan.K, block, &occ);
+    if (e != hipSuccess) return hip_error(e, "occupancy query");
+    int64_t per_cu = plan.waves_per_cu / waves_per_block;
+    if (per_cu < 1) per_cu = 1;
+    if (occ > 0 && per_cu > occ) per_cu = occ;  // one round of resident workgroups
+    int64_t grid = int64_t(dev.cus) * per_cu;
     const int64_t need = (Q + block - 1) / block;
-    if (grid > need) grid = ((need + 7) / 8) * 8;  // keep every XCD served
+    if (grid > need) grid = need;
+    if (grid > 8 && grid % 8) grid -= grid % 8;
     if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(zero_u32, dim3(unsigned((grid + 255) / 256)), dim3(256), 0, st, counter, int(grid));
+    KD_HIP(hipGetLastError());
     hipEvent_t ev0;
     s = timing_begin(st, &ev0);
     if (s != KD_OK) return s;
