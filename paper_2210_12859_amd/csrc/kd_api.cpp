@@ -115,14 +115,14 @@ void pack_records(const float* pts, const int32_t* order, int64_t N, std::vector
     TreeRec<D>* r = reinterpret_cast<TreeRec<D>*>(out.data());
     for (int64_t pos = 0; pos < N; ++pos) {
         const int32_t i = order[pos];
-        for (int j = 0; j < D; ++j) r[pos].c[j] = pts[int64_t(i) * D + j];
-        r[pos].idx = i;
+        for (int j = 0; j < D; ++j) std::memcpy(&r[pos].w[j], &pts[int64_t(i) * D + j], 4);
+        r[pos].w[D] = uint32_t(i);
         // ancestors by 1-based id: a = (pos+1) >> m, level floor(log2 a)
         int64_t a = (pos + 1) >> 1;
-        for (int m = 0; m < 7 - D; ++m, a >>= 1) {
+        for (int m = 0; m < rec_ancestors(D); ++m, a >>= 1) {
             if (a < 1) break;
             const int lvl = 63 - __builtin_clzll((unsigned long long)a);
-            r[pos].anc[m] = pts[int64_t(order[a - 1]) * D + (lvl % D)];
+            std::memcpy(&r[pos].w[D + 1 + m], &pts[int64_t(order[a - 1]) * D + (lvl % D)], 4);
         }
     }
 }

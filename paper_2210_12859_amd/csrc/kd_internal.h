@@ -22,16 +22,23 @@ struct alignas(16) NodeRec {
     int32_t idx;
 };
 
-// Tree node record, 32 bytes: the D coordinates, the caller index, then the
-// split values of the 7 - D nearest ancestors, parent first (the coordinate of
-// the ancestor's point in that ancestor's split dimension).  The ancestor
-// splits let a lane resolve several consecutive "return to parent" steps of
-// the traversal from the record it already holds, without loading the parents.
+// Tree node record: RW = rec_words(D) 32-bit words per level-order position:
+// w[0..D-1] the coordinates, w[D] the caller index, then the split values of
+// the RW - D - 1 nearest ancestors, parent first (the coordinate of the
+// ancestor's point in that ancestor's split dimension).  Ancestor splits let
+// a lane resolve "return to parent" steps of the traversal from the record it
+// already holds, without loading the parent.  D = 3 uses 16-byte records
+// (one dwordx4 per node, eight nodes per 128-byte cache line, no ancestor);
+// D = 2 keeps one ancestor in 16 bytes; D = 4 uses 32 bytes with three.
+#ifndef KD_REC_WORDS_D3
+#define KD_REC_WORDS_D3 4
+#endif
+constexpr int rec_words(int D) { return D == 2 ? 4 : (D == 3 ? KD_REC_WORDS_D3 : 8); }
+constexpr int rec_ancestors(int D) { return rec_words(D) - D - 1; }
+
 template <int D>
-struct alignas(32) TreeRec {
-    float c[D];
-    int32_t idx;
-    float anc[7 - D];
+struct alignas(4 * rec_words(D)) TreeRec {
+    uint32_t w[rec_words(D)];
 };
 
 // Tuned launch parameters kept with a tree (filled by kd_autotune).

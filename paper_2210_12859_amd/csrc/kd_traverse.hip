@@ -36,7 +36,8 @@
 //   * each wave pulls 64 queries at a time with one coalesced load and hands
 //     them to idle lanes by cross-lane shuffle, so a lane restarts without a
 //     memory round trip;
-//   * nodes are 32-byte records loaded as two dwordx4 from one cache line;
+//   * nodes are 16-byte records (D = 2, 3: one dwordx4 per node) or 32-byte
+//     records (D = 4: two dwordx4 from one cache line);
 //   * the k-best list lives in VGPRs as 64-bit keys (d2 bits << 32 | index),
 //     so the lexicographic (d2, index) order is one unsigned compare (d2 >= 0,
 //     and the bit pattern of a non-negative float is monotone); insertion is
@@ -101,17 +102,24 @@ __device__ __forceinline__ float sel_rot(const float (&v)[D], int dim, int I) {
     return r;
 }
 
-// Whole-record loads (two dwordx4 from one 32-byte aligned record).
+// Whole-record loads: one or two dwordx4 from one aligned record.
 template <int D>
-__device__ __forceinline__ void load_tree(const TreeRec<D>* p, float (&c)[D], int32_t& idx, float (&anc)[7 - D]) {
+__device__ __forceinline__ void load_tree(const TreeRec<D>* p, float (&c)[D], int32_t& idx,
+                                          float (&anc)[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1]) {
+    constexpr int RW = rec_words(D);
+    uint32_t w[8];
     const uint4 lo = reinterpret_cast<const uint4*>(p)[0];
-    const uint4 hi = reinterpret_cast<const uint4*>(p)[1];
-    const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    w[0] = lo.x; w[1] = lo.y; w[2] = lo.z; w[3] = lo.w;
+    if (RW == 8) {
+        const uint4 hi = reinterpret_cast<const uint4*>(p)[1];
+        w[4] = hi.x; w[5] = hi.y; w[6] = hi.z; w[7] = hi.w;
+    }
 #pragma unroll
     for (int j = 0; j < D; ++j) c[j] = __uint_as_float(w[j]);
     idx = int32_t(w[D]);
+    anc[0] = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 7 - D; ++j) anc[j] = __uint_as_float(w[D + 1 + j]);
+    for (int j = 0; j < rec_ancestors(D); ++j) anc[j] = __uint_as_float(w[D + 1 + j]);
 }
 
 // Query records (16 bytes for D <= 3, 32 for D = 4).
@@ -213,7 +221,8 @@ __device__ __forceinline__ void lane_finish(const Lane<D, K>& s, const TravArgs&
 // steps.  Returns the new curr (0 = traversal finished).
 template <int D, int K, int F>
 __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D], int32_t idx,
-                                             const float (&anc)[7 - D], int32_t N) {
+                                             const float (&anc)[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1],
+                                             int32_t N) {
     const int32_t curr = s.curr;
     const int dim = (31 - __clz(curr)) % D;  // level of curr, mod D
     float dx[D];
@@ -384,7 +393,7 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
         if (active) {
             float c[D];
             int32_t idx;
-            float anc[7 - D];
+            float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
             load_tree<D>(g1 + s.curr, c, idx, anc);
             const int32_t next = lane_step<D, K, F>(s, c, idx, anc, a.N);
             if (next == 0) {
@@ -417,7 +426,7 @@ __global__ void zero_u32(uint32_t* p, int n) {
 #ifndef KD_FUSED_LEVELS
 #define KD_FUSED_LEVELS 1
 #endif
-constexpr int fused_levels(int D) { return KD_FUSED_LEVELS < 7 - D ? KD_FUSED_LEVELS : 7 - D; }
+constexpr int fused_levels(int D) { return KD_FUSED_LEVELS < rec_ancestors(D) ? KD_FUSED_LEVELS : rec_ancestors(D); }
 
 template <int D, int K>
 hipError_t launch_knn(const TravArgs& a, int block, int grid, hipStream_t st) {
