@@ -125,6 +125,113 @@ kd_status kd_knn_ex(kd_tree t, const float* queries, int64_t Q, int k, float max
                     int32_t* out_idx, float* out_d2, uint32_t* visited,
                     const kd_opts* opts, kd_stream stream);
 
+/* ------------------------------------------------- learned initial radius */
+
+/* A small MLP (3 -> 64 -> 64 -> 1, ReLU; bfloat16 operands, float32
+ * accumulation, trained on the GPU) predicts y ~ ln(distance to the k-th
+ * neighbour) for each query.  A learned query starts its traversal from the
+ * squared radius worst0 = min(R2, fl32(r0 * r0)), r0 = exp(y + margin), in
+ * place of R2 (the search radius of Sec. 3 may start at any value that
+ * contains the answer), and skips the descent through nodes whose splitting
+ * plane lies outside worst0.  Every query that finds fewer than k points
+ * within worst0 < R2 is run again from R2.  Results are therefore
+ * byte-identical to kd_knn for ANY model: the model changes speed only.
+ * The model is 3-D (trees of dim 3). */
+
+typedef struct {
+    int epochs;            /* passes over the training queries (default 20) */
+    int batch;             /* samples per Adam step, 64 .. 2^20 (default 8192) */
+    float lr;              /* Adam learning rate (default 1e-3; betas 0.9, 0.999) */
+    uint64_t seed;         /* weight init and shuffling (default 0) */
+    int64_t holdout;       /* last rows of train_q held out to set the margin;
+                              0 = min(Qt/10, 100000) */
+    float margin_quantile; /* margin = this quantile of held-out (label - y),
+                              0..1 (default 0.95) */
+} kd_train_opts;
+
+typedef struct {
+    int64_t queries;       /* queries in the call */
+    int64_t fallbacks;     /* queries re-run from R2 */
+} kd_stats;
+
+/* Trains a radius model for k on the tree: labels are the k-th neighbour
+ * distances of train_q (device float32 [Qt][3], 128 <= Qt < 2^31) from the
+ * plain traversal; forward, backward and Adam run in the library's HIP
+ * kernels.  Weights start He-normal (seeded), biases at zero except the
+ * output bias, which starts at the mean training label.  opts may be NULL.
+ * Synchronises the stream. */
+kd_status kd_radius_model_train(kd_tree t, const float* train_q, int64_t Qt, int k, const kd_train_opts* opts,
+                                kd_model* out, kd_stream stream);
+
+/* kd_knn with the model's initial radius (see above).  visited (nullable,
+ * device uint32 [Q]) counts processed nodes of both passes; stats (nullable,
+ * HOST) receives the fallback count, which synchronises the stream. */
+kd_status kd_knn_learned(kd_tree t, kd_model m, const float* queries, int64_t Q, int k, float maxRadius,
+                         int32_t* out_idx, float* out_d2, uint32_t* visited, kd_stats* stats, const kd_opts* opts,
+                         kd_stream stream);
+
+/* The same two-pass query with caller radii: r0 is device float32 [Q] in
+ * caller order (any value: NaN, negative or +inf means "no initial radius").
+ * fell_back (nullable, device uint8 [Q]) receives 1 for queries re-run from
+ * R2.  For checking the exact-fallback rule with arbitrary radii. */
+kd_status kd_knn_with_radius(kd_tree t, const float* r0, const float* queries, int64_t Q, int k, float maxRadius,
+                             int32_t* out_idx, float* out_d2, uint32_t* visited, uint8_t* fell_back,
+                             const kd_opts* opts, kd_stream stream);
+
+/* Model facts; loss_curve (HOST, nullable) receives up to loss_cap per-epoch
+ * mean training losses. */
+kd_status kd_model_info(kd_model m, int* k, float* margin, float* holdout_rmse, int* n_epochs, float* loss_curve,
+                        int loss_cap);
+/* HOST copies of the 4481 float32 parameters (order W1[64][3], b1[64],
+ * W2[64][64], b2[64], w3[64], b3) and the input normalisation (lo, 1/extent). */
+kd_status kd_model_get_params(kd_model m, float* host_params, float* lo3, float* inv3);
+/* A model from HOST parameters (same order), normalisation and margin. */
+kd_status kd_model_create(const float* host_params, const float* lo3, const float* inv3, float margin, int k,
+                          kd_model* out);
+kd_status kd_model_save(kd_model m, const char* path);
+kd_status kd_model_load(const char* path, kd_model* out);
+kd_status kd_model_free(kd_model m);
+
+/* Test hooks.  kd_mlp_predict: y (device float32 [n]) for device queries
+ * [n][3].  kd_mlp_grad: mean-squared-error loss and its gradient (HOST
+ * float32 [4481], parameter order) for device queries [n][3] and device
+ * targets [n], n <= 2^20; synchronises the stream. */
+kd_status kd_mlp_predict(kd_model m, const float* queries, int64_t n, float* y, kd_stream stream);
+kd_status kd_mlp_grad(kd_model m, const float* queries, const float* targets, int64_t n, float* host_grad,
+                      float* host_loss, kd_stream stream);
+
+/* ---------------------------------------------------------------- batched */
+
+/* Many independent trees and query sets in one call.  Jobs are grouped by
+ * (dimension, list size); each group runs as ONE persistent traversal launch
+ * in which every lane carries its own tree, after a Morton sort of the
+ * group's queries (each job along its own tree's curve).  Per job, results
+ * are exactly those of kd_knn on that job. */
+typedef struct {
+    kd_tree tree;
+    const float* queries;  /* device [Q][dim] */
+    int64_t Q;
+    int k;                 /* 1..64 */
+    float maxRadius;
+    int32_t* out_idx;      /* device [Q][k] */
+    float* out_d2;         /* device [Q][k] or NULL */
+} kd_job;
+
+typedef struct kd_batch_s* kd_batch;
+
+/* Validates the jobs, allocates the batch's scratch (owned by the batch) and
+ * captures the whole pipeline into a hipGraph (on a private stream when
+ * stream is NULL).  The job pointers are baked into the graph: they must stay
+ * valid for the batch's lifetime.  opts (nullable): block, waves_per_cu and
+ * sort_bits apply to every group. */
+kd_status kd_batch_create(const kd_job* jobs, int n_jobs, const kd_opts* opts, kd_stream stream, kd_batch* out);
+/* Replays the captured graph on stream (asynchronous). */
+kd_status kd_batch_run(kd_batch b, kd_stream stream);
+/* Frees the batch; the caller must have synchronised every stream it ran on. */
+kd_status kd_batch_free(kd_batch b);
+/* create + run + synchronise + free. */
+kd_status kd_knn_batched(const kd_job* jobs, int n_jobs, const kd_opts* opts, kd_stream stream);
+
 /* ------------------------------------------------------------ timing */
 
 /* Kernel timing for benchmarks.  While enabled, every launch of the library's

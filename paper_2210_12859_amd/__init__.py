@@ -31,6 +31,21 @@ class KdError(RuntimeError):
         self.status = status
 
 
+class KdTrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint64), ("holdout", ctypes.c_int64), ("margin_quantile", ctypes.c_float)]
+
+
+class KdStats(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_int64), ("fallbacks", ctypes.c_int64)]
+
+
+class KdJob(ctypes.Structure):
+    _fields_ = [("tree", ctypes.c_void_p), ("queries", ctypes.c_void_p), ("Q", ctypes.c_int64),
+                ("k", ctypes.c_int), ("maxRadius", ctypes.c_float), ("out_idx", ctypes.c_void_p),
+                ("out_d2", ctypes.c_void_p)]
+
+
 class KdOpts(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("lds_levels", ctypes.c_int),
                 ("sort_bits", ctypes.c_int), ("waves_per_cu", ctypes.c_int)]
@@ -55,6 +70,21 @@ def lib():
         "kd_fcp": ([P, P, i64, f32, P, P, P], i32),
         "kd_knn": ([P, P, i64, i32, f32, P, P, P], i32),
         "kd_knn_ex": ([P, P, i64, i32, f32, P, P, P, P, P], i32),
+        "kd_radius_model_train": ([P, P, i64, i32, P, P, P], i32),
+        "kd_knn_learned": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
+        "kd_knn_with_radius": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
+        "kd_model_info": ([P, P, P, P, P, P, i32], i32),
+        "kd_model_get_params": ([P, P, P, P], i32),
+        "kd_model_create": ([P, P, P, f32, i32, P], i32),
+        "kd_model_save": ([P, ctypes.c_char_p], i32),
+        "kd_model_load": ([ctypes.c_char_p, P], i32),
+        "kd_model_free": ([P], i32),
+        "kd_mlp_predict": ([P, P, i64, P, P], i32),
+        "kd_mlp_grad": ([P, P, P, i64, P, P, P], i32),
+        "kd_batch_create": ([P, i32, P, P, P], i32),
+        "kd_batch_run": ([P, P], i32),
+        "kd_batch_free": ([P], i32),
+        "kd_knn_batched": ([P, i32, P, P], i32),
         "kd_timing_enable": ([i32], i32),
         "kd_timing_collect": ([ctypes.c_char_p, P, P], i32),
         "kd_status_str": ([i32], ctypes.c_char_p),
@@ -224,6 +254,189 @@ def kd_knn_ex(tree: Tree, queries, k, max_radius=math.inf, out_idx=None, out_d2=
     _check(lib().kd_knn_ex(tree.handle, _ptr(queries), queries.shape[0], int(k), float(max_radius),
                            _ptr(out_idx), _ptr(out_d2), _ptr(visited), _opts(opts), _stream_handle(stream)))
     return out_idx, out_d2, visited
+
+
+MLP_NPARAM = 4481
+
+
+class Model:
+    """Handle of a kd_model (learned initial-radius MLP)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("model is closed")
+        return self._h
+
+    def info(self):
+        k = ctypes.c_int()
+        margin = ctypes.c_float()
+        rmse = ctypes.c_float()
+        ne = ctypes.c_int()
+        curve = (ctypes.c_float * 1024)()
+        _check(lib().kd_model_info(self.handle, ctypes.byref(k), ctypes.byref(margin), ctypes.byref(rmse),
+                                   ctypes.byref(ne), curve, 1024))
+        return dict(k=k.value, margin=margin.value, holdout_rmse=rmse.value,
+                    loss_curve=list(curve)[: min(ne.value, 1024)])
+
+    def params(self):
+        import numpy as np
+        p = np.empty(MLP_NPARAM, np.float32)
+        lo = np.empty(3, np.float32)
+        inv = np.empty(3, np.float32)
+        _check(lib().kd_model_get_params(self.handle, p.ctypes.data_as(ctypes.c_void_p),
+                                         lo.ctypes.data_as(ctypes.c_void_p), inv.ctypes.data_as(ctypes.c_void_p)))
+        return p, lo, inv
+
+    def save(self, path: str):
+        _check(lib().kd_model_save(self.handle, str(path).encode()))
+
+    def close(self):
+        if self._h:
+            lib().kd_model_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kd_radius_model_train(tree: Tree, train_q, k, epochs=20, batch=8192, lr=1e-3, seed=0, holdout=0,
+                          margin_quantile=0.95, stream=None) -> Model:
+    import torch
+    _require(train_q, torch.float32, "train_q")
+    o = KdTrainOpts(int(epochs), int(batch), float(lr), int(seed), int(holdout), float(margin_quantile))
+    h = ctypes.c_void_p()
+    _check(lib().kd_radius_model_train(tree.handle, _ptr(train_q), train_q.shape[0], int(k), ctypes.byref(o),
+                                       ctypes.byref(h), _stream_handle(stream)))
+    return Model(h.value)
+
+
+def kd_model_create(params, lo, inv, margin, k) -> Model:
+    import numpy as np
+    p = np.ascontiguousarray(params, np.float32)
+    lo = np.ascontiguousarray(lo, np.float32)
+    inv = np.ascontiguousarray(inv, np.float32)
+    h = ctypes.c_void_p()
+    _check(lib().kd_model_create(p.ctypes.data_as(ctypes.c_void_p), lo.ctypes.data_as(ctypes.c_void_p),
+                                 inv.ctypes.data_as(ctypes.c_void_p), float(margin), int(k), ctypes.byref(h)))
+    return Model(h.value)
+
+
+def kd_model_load(path) -> Model:
+    h = ctypes.c_void_p()
+    _check(lib().kd_model_load(str(path).encode(), ctypes.byref(h)))
+    return Model(h.value)
+
+
+def kd_knn_learned(tree: Tree, model: Model, queries, k, max_radius=math.inf, out_idx=None, out_d2=None,
+                   visited=None, want_d2=True, want_visited=False, want_stats=False, opts=None, stream=None):
+    """Returns (idx, d2, visited, stats dict or None)."""
+    import torch
+    _require(queries, torch.float32, "queries")
+    out_idx, out_d2 = _outputs(queries, k, out_idx, out_d2, want_d2)
+    if visited is None and want_visited:
+        visited = torch.empty(queries.shape[0], dtype=torch.int32, device=queries.device)
+    st = KdStats() if want_stats else None
+    _check(lib().kd_knn_learned(tree.handle, model.handle, _ptr(queries), queries.shape[0], int(k),
+                                float(max_radius), _ptr(out_idx), _ptr(out_d2), _ptr(visited),
+                                ctypes.byref(st) if st is not None else None, _opts(opts), _stream_handle(stream)))
+    stats = dict(queries=st.queries, fallbacks=st.fallbacks) if st is not None else None
+    return out_idx, out_d2, visited, stats
+
+
+def kd_knn_with_radius(tree: Tree, r0, queries, k, max_radius=math.inf, out_idx=None, out_d2=None, visited=None,
+                       fell_back=None, want_d2=True, want_visited=False, want_flags=False, opts=None, stream=None):
+    """Returns (idx, d2, visited, fell_back uint8)."""
+    import torch
+    _require(queries, torch.float32, "queries")
+    _require(r0, torch.float32, "r0", (queries.shape[0],))
+    out_idx, out_d2 = _outputs(queries, k, out_idx, out_d2, want_d2)
+    if visited is None and want_visited:
+        visited = torch.empty(queries.shape[0], dtype=torch.int32, device=queries.device)
+    if fell_back is None and want_flags:
+        fell_back = torch.empty(queries.shape[0], dtype=torch.uint8, device=queries.device)
+    _check(lib().kd_knn_with_radius(tree.handle, _ptr(r0), _ptr(queries), queries.shape[0], int(k),
+                                    float(max_radius), _ptr(out_idx), _ptr(out_d2), _ptr(visited), _ptr(fell_back),
+                                    _opts(opts), _stream_handle(stream)))
+    return out_idx, out_d2, visited, fell_back
+
+
+def kd_mlp_predict(model: Model, queries, out=None, stream=None):
+    import torch
+    _require(queries, torch.float32, "queries")
+    if out is None:
+        out = torch.empty(queries.shape[0], dtype=torch.float32, device=queries.device)
+    _check(lib().kd_mlp_predict(model.handle, _ptr(queries), queries.shape[0], _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def kd_mlp_grad(model: Model, queries, targets, stream=None):
+    """(loss, gradient as a numpy float32 [4481])."""
+    import numpy as np
+    import torch
+    _require(queries, torch.float32, "queries")
+    _require(targets, torch.float32, "targets", (queries.shape[0],))
+    g = np.empty(MLP_NPARAM, np.float32)
+    loss = ctypes.c_float()
+    _check(lib().kd_mlp_grad(model.handle, _ptr(queries), _ptr(targets), queries.shape[0],
+                             g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss), _stream_handle(stream)))
+    return loss.value, g
+
+
+def _job_array(jobs):
+    """jobs: list of dicts {tree, queries, k, max_radius=inf, out_idx, out_d2=None}."""
+    import torch
+    arr = (KdJob * max(1, len(jobs)))()
+    for i, j in enumerate(jobs):
+        q = j["queries"]
+        _require(q, torch.float32, f"jobs[{i}].queries")
+        _require(j["out_idx"], torch.int32, f"jobs[{i}].out_idx")
+        if j["out_idx"].numel() != q.shape[0] * j["k"]:
+            raise ValueError(f"jobs[{i}].out_idx must hold Q*k entries")
+        d2 = j.get("out_d2")
+        if d2 is not None:
+            _require(d2, torch.float32, f"jobs[{i}].out_d2")
+            if d2.numel() != q.shape[0] * j["k"]:
+                raise ValueError(f"jobs[{i}].out_d2 must hold Q*k entries")
+        arr[i] = KdJob(j["tree"].handle, q.data_ptr(), q.shape[0], int(j["k"]), float(j.get("max_radius", math.inf)),
+                       j["out_idx"].data_ptr(), d2.data_ptr() if d2 is not None else None)
+    return arr
+
+
+class Batch:
+    """A captured batched pipeline (kd_batch); run() replays its hipGraph."""
+
+    def __init__(self, jobs, opts=None, stream=None):
+        self._jobs = jobs  # keep the tensors alive
+        arr = _job_array(jobs)
+        h = ctypes.c_void_p()
+        _check(lib().kd_batch_create(arr, len(jobs), _opts(opts), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(lib().kd_batch_run(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if self._h:
+            lib().kd_batch_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kd_knn_batched(jobs, opts=None, stream=None):
+    arr = _job_array(jobs)
+    _check(lib().kd_knn_batched(arr, len(jobs), _opts(opts), _stream_handle(stream)))
 
 
 def kd_timing_enable(on: bool = True):

@@ -28,6 +28,9 @@ SOURCES = [
     ("kd_build_host.cpp", False),
     ("kd_traverse.hip", True),
     ("kd_sort.hip", True),
+    ("kd_mlp.hip", True),
+    ("kd_model.cpp", True),
+    ("kd_batch.cpp", True),
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",

@@ -223,6 +223,15 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
 
 }  // namespace
 
+kd_status resolve_plan_public(kd_tree t, int k, float maxRadius, const kd_opts* o, QueryPlan& p) {
+    return resolve_plan(t, k, maxRadius, o, p);
+}
+
+kd_status check_query_args_public(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius,
+                                  const int32_t* out_idx, const char* fn) {
+    return check_query_args(t, queries, Q, k, maxRadius, out_idx, fn);
+}
+
 kd_status knn_entry(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius, int32_t* out_idx,
                     float* out_d2, uint32_t* visited, const kd_opts* opts, kd_stream stream, const char* fn) {
     kd_status s = check_query_args(t, queries, Q, k, maxRadius, out_idx, fn);

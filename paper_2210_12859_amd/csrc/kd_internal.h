@@ -27,11 +27,11 @@ struct alignas(16) NodeRec {
 // the RW - D - 1 nearest ancestors, parent first (the coordinate of the
 // ancestor's point in that ancestor's split dimension).  Ancestor splits let
 // a lane resolve "return to parent" steps of the traversal from the record it
-// already holds, without loading the parent.  D = 3 uses 16-byte records
-// (one dwordx4 per node, eight nodes per 128-byte cache line, no ancestor);
-// D = 2 keeps one ancestor in 16 bytes; D = 4 uses 32 bytes with three.
+// already holds, without loading the parent.  D = 2 uses 16-byte records
+// (one ancestor); D = 3 and D = 4 use 32-byte records (four and three
+// ancestors), loaded as two dwordx4 from one cache line.
 #ifndef KD_REC_WORDS_D3
-#define KD_REC_WORDS_D3 4
+#define KD_REC_WORDS_D3 8
 #endif
 constexpr int rec_words(int D) { return D == 2 ? 4 : (D == 3 ? KD_REC_WORDS_D3 : 8); }
 constexpr int rec_ancestors(int D) { return rec_words(D) - D - 1; }
@@ -110,11 +110,58 @@ struct QueryPlan {
     int waves_per_cu = 8;
 };
 int k_template(int k);
+
+// One job of a batched call, as the device sees it.  Jobs of one (dim, K)
+// class are laid out back to back in a class slot space.
+struct BatchJob {
+    const void* nodes;       // TreeRec<D>[N], level order
+    const float* queries;    // caller [Q][D]
+    int32_t* out_idx;        // caller [Q][k]
+    float* out_d2;           // caller [Q][k] or NULL
+    float lo[4], scale[4];   // Morton normalisation over the tree's bounding box
+    int32_t N;
+    int32_t k;
+    float R2;
+    uint32_t slot_base;      // first class slot of the job
+    uint32_t Q;
+    int32_t vec_store;
+};
+
+// Learned-radius request: initial squared radius per query from the MLP
+// (params != NULL) or from caller radii r0 (caller order).
+struct LearnedSpec {
+    const float* params;  // device, 4481 floats, or NULL
+    float lo[3], inv[3];
+    float margin;
+    const float* r0;      // device [Q] caller order (when params == NULL)
+    uint8_t* fb_flag;     // device [Q] caller order, nullable
+};
+// Batched class pipeline (kd_sort.hip, kd_traverse.hip)
+size_t batch_sort_scratch_bytes(int64_t n);
+kd_status batch_sort(const BatchJob* d_jobs, int njobs, int dim, uint32_t n, int sort_bits, void* ws,
+                     hipStream_t st, const uint32_t** perm_out);
+kd_status run_batch_class(const BatchJob* d_jobs, int njobs, int dim, int K, uint32_t n, const uint32_t* perm,
+                          void* recs, uint32_t* counters, const QueryPlan& plan, int device, hipStream_t st);
+size_t batch_rec_bytes();
 // Morton reorder of query slots (kd_sort.hip)
 size_t sort_scratch_bytes(int64_t Q);
 kd_status morton_sort(kd_tree t, const float* queries, int64_t Q, int sort_bits, void* ws, hipStream_t st,
                       const uint32_t** perm_out);
-kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan,
-                  int32_t* out_idx, float* out_d2, uint32_t* visited, kd_stream stream);
+kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan, int32_t* out_idx,
+                  float* out_d2, uint32_t* visited, kd_stream stream, const LearnedSpec* learned = nullptr,
+                  uint32_t* fallbacks_out = nullptr);
+
+// ---- MLP kernels (kd_mlp.hip) ---------------------------------------------
+constexpr int MLP_NPARAM = 4481;
+hipError_t launch_mlp_worst0(const float* P, const float* lo, const float* inv, float margin, float R2,
+                             const void* sq, uint32_t Q, float* worst0, hipStream_t st);
+hipError_t launch_mlp_predict(const float* P, const float* lo, const float* inv, const float* qs, uint32_t n,
+                              float* y, hipStream_t st);
+hipError_t launch_mlp_fwd_bwd(const float* P, const float* lo, const float* inv, const float* qs, const float* t,
+                              const uint32_t* idx, uint32_t b0, uint32_t batch, float* part, float* part_loss,
+                              hipStream_t st);
+hipError_t launch_mlp_reduce_adam(const float* part, const float* part_loss, int nparts, uint32_t batch, float* P,
+                                  float* m, float* v, int step, float lr, float* grad, float* loss, hipStream_t st);
+hipError_t launch_knn_label(const float* d2, int k, uint32_t n, float* t, hipStream_t st);
 
 }  // namespace kd

@@ -177,7 +177,77 @@ __global__ __launch_bounds__(SORT_THREADS) void radix_scatter(const uint32_t* __
     }
 }
 
+// Job of class slot i (jobs sorted by slot_base).
+__device__ __forceinline__ int find_job(const BatchJob* jobs, int njobs, uint32_t i) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].slot_base <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// key = job index in the top jb bits, the job-local Morton code below
+__global__ void batch_morton_codes(const BatchJob* __restrict__ jobs, int njobs, int D, int jb, uint32_t n,
+                                   uint32_t* __restrict__ codes, uint32_t* __restrict__ vals) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int j = find_job(jobs, njobs, i);
+    const BatchJob& J = jobs[j];
+    const uint32_t row = i - J.slot_base;
+    const int bits = D == 2 ? 16 : (D == 3 ? 10 : 8);
+    const float maxc = float((1u << bits) - 1);
+    uint32_t code = 0;
+    for (int d = 0; d < D; ++d) {
+        float u = (J.queries[size_t(row) * D + d] - J.lo[d]) * J.scale[d];
+        u = u != u ? 0.0f : fminf(fmaxf(u, 0.0f), maxc);
+        code |= spread_bits(uint32_t(u), D) << (D - 1 - d);
+    }
+    if (D == 3) code <<= 2;
+    codes[i] = jb > 0 ? (uint32_t(j) << (32 - jb)) | (code >> jb) : code;
+    vals[i] = i;
+}
+
 }  // namespace
+
+size_t batch_sort_scratch_bytes(int64_t n) {
+    const size_t ntiles = size_t((n + SORT_TILE - 1) / SORT_TILE);
+    return 4 * size_t(n) * sizeof(uint32_t) + (256 * ntiles + 256) * sizeof(uint32_t) + 256;
+}
+
+kd_status batch_sort(const BatchJob* d_jobs, int njobs, int dim, uint32_t n, int sort_bits, void* ws,
+                     hipStream_t st, const uint32_t** perm_out) {
+    *perm_out = nullptr;
+    if (n <= 1) return KD_OK;
+    int jb = 0;
+    while ((1 << jb) < njobs) ++jb;
+    if (sort_bits <= 0) return KD_OK;  // class slots are already in job order
+    const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+    uint32_t* k0 = reinterpret_cast<uint32_t*>(ws);
+    uint32_t* v0 = k0 + n;
+    uint32_t* k1 = v0 + n;
+    uint32_t* v1 = k1 + n;
+    uint32_t* hist = v1 + n;
+    uint32_t* totals = hist + size_t(256) * ntiles;
+    hipLaunchKernelGGL(batch_morton_codes, dim3((n + 255) / 256), dim3(256), 0, st, d_jobs, njobs, dim, jb, n, k0, v0);
+    KD_HIP(hipGetLastError());
+    // the job bits must take part in the sort: sort on at least jb top bits
+    int bits = sort_bits < jb ? ((jb + 7) / 8) * 8 : sort_bits;
+    if (bits > 32) bits = 32;
+    for (int p = 0; p < bits / 8; ++p) {
+        const int shift = 32 - bits + 8 * p;
+        hipLaunchKernelGGL(radix_hist, dim3(ntiles), dim3(SORT_THREADS), 0, st, k0, n, shift, hist, ntiles);
+        hipLaunchKernelGGL(radix_scan, dim3(256), dim3(SORT_THREADS), 0, st, hist, ntiles, totals);
+        hipLaunchKernelGGL(radix_scatter, dim3(ntiles), dim3(SORT_THREADS), 0, st, k0, v0, n, shift, hist, ntiles,
+                           totals, k1, v1);
+        KD_HIP(hipGetLastError());
+        uint32_t* tk = k0; k0 = k1; k1 = tk;
+        uint32_t* tv = v0; v0 = v1; v1 = tv;
+    }
+    *perm_out = v0;
+    return KD_OK;
+}
 
 size_t sort_scratch_bytes(int64_t Q) {
     const size_t ntiles = size_t((Q + SORT_TILE - 1) / SORT_TILE);

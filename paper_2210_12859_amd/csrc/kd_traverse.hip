@@ -36,8 +36,8 @@
 //   * each wave pulls 64 queries at a time with one coalesced load and hands
 //     them to idle lanes by cross-lane shuffle, so a lane restarts without a
 //     memory round trip;
-//   * nodes are 16-byte records (D = 2, 3: one dwordx4 per node) or 32-byte
-//     records (D = 4: two dwordx4 from one cache line);
+//   * nodes are 16-byte records (D = 2: one dwordx4) or 32-byte records
+//     (D = 3, 4: two dwordx4 from one cache line);
 //   * the k-best list lives in VGPRs as 64-bit keys (d2 bits << 32 | index),
 //     so the lexicographic (d2, index) order is one unsigned compare (d2 >= 0,
 //     and the bit pattern of a non-negative float is monotone); insertion is
@@ -64,6 +64,15 @@ struct TravArgs {
     uint32_t* visited;       // [Q] or NULL
     uint32_t* counter;       // [gridDim.x] per-workgroup range cursors, zero at launch
     int vec_store;           // outputs 16-byte aligned with k % 4 == 0: vector stores
+    // learned-radius pass
+    const float* worst0;     // [Q] initial squared radius per slot (learned kernels)
+    uint32_t* fb_list;       // slots whose learned pass found < k points (learned kernels)
+    uint32_t* fb_count;
+    uint8_t* fb_flag;        // [Q] caller order, 1 = fell back (nullable)
+    // indirect pass: query slots are slot_list[0 .. *slot_count)
+    const uint32_t* slot_list;
+    const uint32_t* slot_count;
+    int visited_add;         // add to visited[] instead of storing
 };
 
 __device__ __forceinline__ uint64_t make_key(float d2, int32_t idx) {
@@ -152,34 +161,61 @@ __device__ __forceinline__ NodeRec<D> shfl_rec(const NodeRec<D>& r, int src) {
 // Per-lane query state: the two node ids of the state machine (1-based),
 // the split dimension of `curr` (implied by its level, tracked as the lane
 // moves), the query and its k-best list.
+//
+// Learned-radius lanes start from worst0 <= R2 instead of R2.  They first
+// descend from the root along close children while the splitting plane is
+// farther than the radius (sd^2 > worst0): such a node's point has
+// d2 >= sd^2 > worst0 and its far subtree is farther still, so neither can
+// enter the list; the traversal proper then starts at the first node whose
+// plane is within range, and ends when it returns to that node's parent
+// (`stop`).  Plain lanes have stop = 0, the root's parent.
 template <int D, int K>
 struct Lane {
     float q[D];
     uint64_t L[K];
     int32_t curr, prev;
-    int dim;
+    int32_t stop;      // returning to this id ends the traversal
     int32_t row;
+    uint32_t slot;
     uint32_t vis;
+    float w0;          // initial squared radius
+    bool skipping;     // still in the learned start-node descent
 };
 
-template <int D, int K>
-__device__ __forceinline__ void lane_start(Lane<D, K>& s, const TravArgs& a, const NodeRec<D>& qr) {
+template <int D, int K, bool LEARNED>
+__device__ __forceinline__ void lane_start(Lane<D, K>& s, const TravArgs& a, const NodeRec<D>& qr, uint32_t slot,
+                                           float w0) {
 #pragma unroll
     for (int j = 0; j < D; ++j) s.q[j] = qr.c[j];
     s.row = qr.idx;
+    s.slot = slot;
+    s.w0 = LEARNED ? w0 : a.R2;
     // Slots beyond k hold the smallest key so the list's worst entry is the
     // k-th real one; real keys are >= 0 and never move in front of them.
-    const uint64_t sent = make_key(a.R2, SENT_IDX);
+    const uint64_t sent = make_key(s.w0, SENT_IDX);
 #pragma unroll
     for (int j = 0; j < K; ++j) s.L[j] = (j < K - a.k) ? uint64_t(0) : sent;
     s.curr = 1;   // root
     s.prev = 0;   // the root's parent
-    s.dim = 0;
+    s.stop = 0;
     s.vis = 0;
+    s.skipping = LEARNED;
 }
 
-template <int D, int K>
+template <int D, int K, bool LEARNED>
 __device__ __forceinline__ void lane_finish(const Lane<D, K>& s, const TravArgs& a) {
+    if (LEARNED) {
+        // fewer than k points within worst0 < R2: the result may be
+        // incomplete, so the query is re-run from R2 in the second pass
+        const bool fell_back = uint32_t(s.L[K - 1]) == SENT_IDX && s.w0 < a.R2;
+        if (a.fb_flag) a.fb_flag[s.row] = fell_back ? 1 : 0;
+        if (fell_back) {
+            const uint32_t pos = atomicAdd(a.fb_count, 1u);
+            a.fb_list[pos] = s.slot;
+            if (a.visited) a.visited[s.row] = s.vis;
+            return;
+        }
+    }
     int32_t* oi = a.out_idx + int64_t(s.row) * a.k;
     float* od = a.out_d2 ? a.out_d2 + int64_t(s.row) * a.k : nullptr;
     const int off = K - a.k;
@@ -213,13 +249,16 @@ __device__ __forceinline__ void lane_finish(const Lane<D, K>& s, const TravArgs&
             }
         }
     }
-    if (a.visited) a.visited[s.row] = s.vis;
+    if (a.visited) {
+        if (a.visited_add) a.visited[s.row] += s.vis;
+        else a.visited[s.row] = s.vis;
+    }
 }
 
 // One loop trip for a lane at node s.curr (record fields c, idx, anc):
 // the state-machine step at curr, then up to F fused "return to parent"
 // steps.  Returns the new curr (0 = traversal finished).
-template <int D, int K, int F>
+template <int D, int K, int F, bool LEARNED>
 __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D], int32_t idx,
                                              const float (&anc)[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1],
                                              int32_t N) {
@@ -229,6 +268,18 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
 #pragma unroll
     for (int j = 0; j < D; ++j) dx[j] = s.q[j] - c[j];
     const float sd = sel_rot<D>(dx, dim, 0);
+    if (LEARNED && s.skipping) {
+        if (sd * sd > s.w0) {
+            // skip: node and far subtree are out of range; follow the close child
+            const int32_t close_c = (curr << 1) | (sd > 0.0f ? 1 : 0);
+            const int32_t next = close_c <= N ? close_c : s.stop;  // nothing in range: finish
+            s.prev = curr;
+            s.curr = next;
+            return next;
+        }
+        s.skipping = false;
+        s.stop = curr >> 1;  // the traversal proper starts here (prev < curr)
+    }
 
     const bool from_parent = s.prev < curr;
     // processNode on the first visit: exact binary32 squared distance, left
@@ -260,7 +311,7 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     // keep returning.
 #pragma unroll
     for (int i = 0; i < F; ++i) {
-        const bool live = up & (anc_id != 0);
+        const bool live = up & (anc_id != s.stop);
         if (__any(live)) {
             if (live) {
                 const float sda = sel_rot<D>(s.q, dim, i + 1) - anc[i];
@@ -279,7 +330,7 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
         }
     }
     if (up) {
-        next = anc_id;  // 0 once the root has returned: finished
+        next = anc_id;  // == stop once the start node has returned: finished
         nprev = child;
     }
     s.prev = nprev;
@@ -340,17 +391,21 @@ __device__ __forceinline__ uint32_t group_range(uint32_t g, uint32_t G) {
 
 constexpr int max_block(int K) { return K >= 32 ? 256 : 1024; }
 
-template <int D, int K, int F>
+template <int D, int K, int F, bool LEARNED>
 __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
     const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes) - 1;  // 1-based
     const NodeRec<D>* __restrict__ sq = reinterpret_cast<const NodeRec<D>*>(a.sq);
+    if (a.slot_count) a.Q = *a.slot_count;  // indirect pass: count produced on the device
 
     const uint32_t lane = __lane_id();
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
     WorkSource ws{group_range(blockIdx.x, gridDim.x), gridDim.x, 0u, 64u, blockDim.x >> 6, false};
     // Query chunk held across the wave: lane l holds slot cb + l of the
-    // current chunk; idle lanes take queries from it by cross-lane shuffle.
+    // current chunk (record, slot index, initial radius); idle lanes take
+    // queries from it by cross-lane shuffle.
     NodeRec<D> chunk;
+    uint32_t chunk_slot = 0;
+    float chunk_w0 = 0.0f;
     uint32_t cpos = 0, cn = 0;
 
     Lane<D, K> s;
@@ -362,9 +417,12 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
             const uint32_t rank = __popcll(need & lt_mask);
             const uint32_t take1 = n < cn - cpos ? n : cn - cpos;
             {
-                const NodeRec<D> v = shfl_rec<D>(chunk, int(cpos + (rank < take1 ? rank : 0)));
+                const int src = int(cpos + (rank < take1 ? rank : 0));
+                const NodeRec<D> v = shfl_rec<D>(chunk, src);
+                const uint32_t vs = __shfl(chunk_slot, src);
+                const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
                 if (!active && rank < take1) {
-                    lane_start<D, K>(s, a, v);
+                    lane_start<D, K, LEARNED>(s, a, v, vs, vw);
                     active = true;
                 }
             }
@@ -373,13 +431,21 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
                 uint32_t cb = 0, cn2 = 0;
                 ws.grab(a, lane, cb, cn2);
                 if (cn2) {
-                    if (lane < cn2) chunk = load_query<D>(sq + cb + lane);
+                    if (lane < cn2) {
+                        const uint32_t i = cb + lane;
+                        chunk_slot = a.slot_list ? a.slot_list[i] : i;
+                        chunk = load_query<D>(sq + chunk_slot);
+                        if (LEARNED) chunk_w0 = a.worst0[chunk_slot];
+                    }
                     cn = cn2;
                     const uint32_t r2 = rank - take1;
                     const uint32_t take2 = n - take1 < cn2 ? n - take1 : cn2;
-                    const NodeRec<D> v = shfl_rec<D>(chunk, int(r2 < take2 ? r2 : 0));
+                    const int src = int(r2 < take2 ? r2 : 0);
+                    const NodeRec<D> v = shfl_rec<D>(chunk, src);
+                    const uint32_t vs = __shfl(chunk_slot, src);
+                    const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
                     if (!active && rank >= take1 && r2 < take2) {
-                        lane_start<D, K>(s, a, v);
+                        lane_start<D, K, LEARNED>(s, a, v, vs, vw);
                         active = true;
                     }
                     cpos = take2;
@@ -395,9 +461,9 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
             int32_t idx;
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
             load_tree<D>(g1 + s.curr, c, idx, anc);
-            const int32_t next = lane_step<D, K, F>(s, c, idx, anc, a.N);
-            if (next == 0) {
-                lane_finish<D, K>(s, a);
+            const int32_t next = lane_step<D, K, F, LEARNED>(s, c, idx, anc, a.N);
+            if (next == s.stop) {
+                lane_finish<D, K, LEARNED>(s, a);
                 active = false;
             }
         }
@@ -429,21 +495,24 @@ __global__ void zero_u32(uint32_t* p, int n) {
 constexpr int fused_levels(int D) { return KD_FUSED_LEVELS < rec_ancestors(D) ? KD_FUSED_LEVELS : rec_ancestors(D); }
 
 template <int D, int K>
-hipError_t launch_knn(const TravArgs& a, int block, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((knn_persistent<D, K, fused_levels(D)>), dim3(grid), dim3(block), 0, st, a);
+hipError_t launch_knn(const TravArgs& a, bool learned, int block, int grid, hipStream_t st) {
+    if (learned)
+        hipLaunchKernelGGL((knn_persistent<D, K, fused_levels(D), true>), dim3(grid), dim3(block), 0, st, a);
+    else
+        hipLaunchKernelGGL((knn_persistent<D, K, fused_levels(D), false>), dim3(grid), dim3(block), 0, st, a);
     return hipGetLastError();
 }
 
 template <int D>
-hipError_t dispatch_k(int K, const TravArgs& a, int block, int grid, hipStream_t st) {
+hipError_t dispatch_k(int K, const TravArgs& a, bool learned, int block, int grid, hipStream_t st) {
     switch (K) {
-        case 1: return launch_knn<D, 1>(a, block, grid, st);
-        case 2: return launch_knn<D, 2>(a, block, grid, st);
-        case 4: return launch_knn<D, 4>(a, block, grid, st);
-        case 8: return launch_knn<D, 8>(a, block, grid, st);
-        case 16: return launch_knn<D, 16>(a, block, grid, st);
-        case 32: return launch_knn<D, 32>(a, block, grid, st);
-        case 64: return launch_knn<D, 64>(a, block, grid, st);
+        case 1: return launch_knn<D, 1>(a, learned, block, grid, st);
+        case 2: return launch_knn<D, 2>(a, learned, block, grid, st);
+        case 4: return launch_knn<D, 4>(a, learned, block, grid, st);
+        case 8: return launch_knn<D, 8>(a, learned, block, grid, st);
+        case 16: return launch_knn<D, 16>(a, learned, block, grid, st);
+        case 32: return launch_knn<D, 32>(a, learned, block, grid, st);
+        case 64: return launch_knn<D, 64>(a, learned, block, grid, st);
     }
     return hipErrorInvalidValue;
 }
@@ -451,7 +520,7 @@ hipError_t dispatch_k(int K, const TravArgs& a, int block, int grid, hipStream_t
 template <int D>
 hipError_t occupancy_k(int K, int block, int* occ) {
     switch (K) {
-#define KD_OCC(KK) case KK: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, knn_persistent<D, KK, fused_levels(D)>, block, 0);
+#define KD_OCC(KK) case KK: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, knn_persistent<D, KK, fused_levels(D), true>, block, 0);
         KD_OCC(1) KD_OCC(2) KD_OCC(4) KD_OCC(8) KD_OCC(16) KD_OCC(32) KD_OCC(64)
 #undef KD_OCC
     }
@@ -467,11 +536,11 @@ hipError_t occupancy(int D, int K, int block, int* occ) {
     return hipErrorInvalidValue;
 }
 
-hipError_t dispatch_dk(int D, int K, const TravArgs& a, int block, int grid, hipStream_t st) {
+hipError_t dispatch_dk(int D, int K, const TravArgs& a, bool learned, int block, int grid, hipStream_t st) {
     switch (D) {
-        case 2: return dispatch_k<2>(K, a, block, grid, st);
-        case 3: return dispatch_k<3>(K, a, block, grid, st);
-        case 4: return dispatch_k<4>(K, a, block, grid, st);
+        case 2: return dispatch_k<2>(K, a, learned, block, grid, st);
+        case 3: return dispatch_k<3>(K, a, learned, block, grid, st);
+        case 4: return dispatch_k<4>(K, a, learned, block, grid, st);
     }
     return hipErrorInvalidValue;
 }
@@ -494,7 +563,286 @@ hipError_t launch_gather(int D, const float* queries, const uint32_t* perm, uint
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ batched jobs
+//
+// Many trees in one launch: the jobs of one (dimension, K) class share a
+// class slot space (jobs back to back, each job's queries Morton-sorted).  A
+// lane carries its job's tree pointer, size, k and output pointers along with
+// the query, so the lanes of one wave may serve different trees; the state
+// machine is the same code as the single-tree kernel.
+
+// Class query record: coordinates, caller row, job index (32 bytes).
+struct alignas(32) BRec {
+    float c[4];
+    int32_t row;
+    int32_t job;
+    int32_t pad[2];
+};
+
+template <int D>
+__global__ void batch_gather(const BatchJob* __restrict__ jobs, int njobs, const uint32_t* __restrict__ perm,
+                             uint32_t n, BRec* __restrict__ recs) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t slot = perm ? perm[i] : i;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].slot_base <= slot) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchJob& J = jobs[lo];
+    const uint32_t row = slot - J.slot_base;
+    BRec r;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) r.c[d] = d < D ? J.queries[size_t(row) * D + d] : 0.0f;
+    r.row = int32_t(row);
+    r.job = lo;
+    r.pad[0] = r.pad[1] = 0;
+    recs[i] = r;
+}
+
+struct BatchArgs {
+    const BatchJob* jobs;
+    const BRec* recs;
+    uint32_t Q;
+    uint32_t* counter;
+};
+
+template <int D, int K>
+struct JobLane {
+    const TreeRec<D>* g1;  // 1-based record pointer of the lane's tree
+    int32_t N;
+    int32_t k;
+    int32_t* oi;
+    float* od;
+    int32_t vec;
+};
+
+template <int D, int K>
+__device__ __forceinline__ void batch_start(Lane<D, K>& s, JobLane<D, K>& j, const BatchJob* jobs,
+                                            const BRec& r) {
+    const BatchJob& J = jobs[r.job];
+    j.g1 = reinterpret_cast<const TreeRec<D>*>(J.nodes) - 1;
+    j.N = J.N;
+    j.k = J.k;
+    j.oi = J.out_idx;
+    j.od = J.out_d2;
+    j.vec = J.vec_store;
+#pragma unroll
+    for (int d = 0; d < D; ++d) s.q[d] = r.c[d];
+    s.row = r.row;
+    s.slot = 0;
+    s.w0 = J.R2;
+    const uint64_t sent = make_key(J.R2, SENT_IDX);
+#pragma unroll
+    for (int e = 0; e < K; ++e) s.L[e] = (e < K - j.k) ? uint64_t(0) : sent;
+    s.curr = 1;
+    s.prev = 0;
+    s.stop = 0;
+    s.vis = 0;
+    s.skipping = false;
+}
+
+template <int D, int K>
+__device__ __forceinline__ void batch_finish(const Lane<D, K>& s, const JobLane<D, K>& j) {
+    int32_t* oi = j.oi + int64_t(s.row) * j.k;
+    float* od = j.od ? j.od + int64_t(s.row) * j.k : nullptr;
+    const int off = K - j.k;
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+        if (e >= off) {
+            const uint32_t id = uint32_t(s.L[e]);
+            const bool empty = id == SENT_IDX;
+            oi[e - off] = empty ? -1 : int32_t(id);
+            if (od) od[e - off] = empty ? __builtin_inff() : key_d2(s.L[e]);
+        }
+    }
+}
+
+__device__ __forceinline__ BRec shfl_brec(const BRec& r, int src) {
+    BRec o;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) o.c[d] = __shfl(r.c[d], src);
+    o.row = __shfl(r.row, src);
+    o.job = __shfl(r.job, src);
+    o.pad[0] = o.pad[1] = 0;
+    return o;
+}
+
+__device__ __forceinline__ BRec load_brec(const BRec* p) {
+    const float4 a = reinterpret_cast<const float4*>(p)[0];
+    const int4 b = reinterpret_cast<const int4*>(p)[1];
+    BRec r;
+    r.c[0] = a.x;
+    r.c[1] = a.y;
+    r.c[2] = a.z;
+    r.c[3] = a.w;
+    r.row = b.x;
+    r.job = b.y;
+    r.pad[0] = r.pad[1] = 0;
+    return r;
+}
+
+template <int D, int K, int F>
+__global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
+    const uint32_t lane = __lane_id();
+    const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
+    // the work source only reads a.Q and a.counter
+    TravArgs wa = {};
+    wa.Q = a.Q;
+    wa.counter = a.counter;
+    WorkSource ws{group_range(blockIdx.x, gridDim.x), gridDim.x, 0u, 64u, blockDim.x >> 6, false};
+    BRec chunk;
+    uint32_t cpos = 0, cn = 0;
+    Lane<D, K> s;
+    JobLane<D, K> j;
+    bool active = false;
+    for (;;) {
+        const uint64_t need = __ballot(!active);
+        if (need && !ws.exhausted) {
+            const uint32_t n = __popcll(need);
+            const uint32_t rank = __popcll(need & lt_mask);
+            const uint32_t take1 = n < cn - cpos ? n : cn - cpos;
+            {
+                const BRec v = shfl_brec(chunk, int(cpos + (rank < take1 ? rank : 0)));
+                if (!active && rank < take1) {
+                    batch_start<D, K>(s, j, a.jobs, v);
+                    active = true;
+                }
+            }
+            cpos += take1;
+            if (n > take1) {
+                uint32_t cb = 0, cn2 = 0;
+                ws.grab(wa, lane, cb, cn2);
+                if (cn2) {
+                    if (lane < cn2) chunk = load_brec(a.recs + cb + lane);
+                    cn = cn2;
+                    const uint32_t r2 = rank - take1;
+                    const uint32_t take2 = n - take1 < cn2 ? n - take1 : cn2;
+                    const BRec v = shfl_brec(chunk, int(r2 < take2 ? r2 : 0));
+                    if (!active && rank >= take1 && r2 < take2) {
+                        batch_start<D, K>(s, j, a.jobs, v);
+                        active = true;
+                    }
+                    cpos = take2;
+                } else {
+                    cn = 0;
+                    cpos = 0;
+                }
+            }
+        }
+        if (!__any(active)) break;
+        if (active) {
+            float c[D];
+            int32_t idx;
+            float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
+            load_tree<D>(j.g1 + s.curr, c, idx, anc);
+            const int32_t next = lane_step<D, K, F, false>(s, c, idx, anc, j.N);
+            if (next == s.stop) {
+                batch_finish<D, K>(s, j);
+                active = false;
+            }
+        }
+    }
+}
+
+template <int D, int K>
+hipError_t launch_batched(const BatchArgs& a, int block, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((knn_batched<D, K, fused_levels(D)>), dim3(grid), dim3(block), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t dispatch_batched_k(int K, const BatchArgs& a, int block, int grid, hipStream_t st) {
+    switch (K) {
+        case 1: return launch_batched<D, 1>(a, block, grid, st);
+        case 2: return launch_batched<D, 2>(a, block, grid, st);
+        case 4: return launch_batched<D, 4>(a, block, grid, st);
+        case 8: return launch_batched<D, 8>(a, block, grid, st);
+        case 16: return launch_batched<D, 16>(a, block, grid, st);
+        case 32: return launch_batched<D, 32>(a, block, grid, st);
+        case 64: return launch_batched<D, 64>(a, block, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int D>
+hipError_t occupancy_batched_k(int K, int block, int* occ) {
+    switch (K) {
+#define KD_OCCB(KK) case KK: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, knn_batched<D, KK, fused_levels(D)>, block, 0);
+        KD_OCCB(1) KD_OCCB(2) KD_OCCB(4) KD_OCCB(8) KD_OCCB(16) KD_OCCB(32) KD_OCCB(64)
+#undef KD_OCCB
+    }
+    return hipErrorInvalidValue;
+}
+
+// worst0[slot] = min(R2, fl(r0 * r0)) for r0 = r0_rows[row of slot]; a
+// non-finite or negative r0 gives R2 (the learned-radius rule).
+template <int D>
+__global__ void radius_to_worst0(const float* __restrict__ r0_rows, const NodeRec<D>* __restrict__ sq, uint32_t Q,
+                                 float R2, float* __restrict__ worst0) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Q) return;
+    const float r0 = r0_rows[sq[i].idx];
+    float w = R2;
+    if (__builtin_isfinite(r0) && r0 >= 0.0f) {
+        const float r2 = r0 * r0;
+        w = r2 < R2 ? r2 : R2;
+    }
+    worst0[i] = w;
+}
+
+hipError_t launch_radius_to_worst0(int D, const float* r0, const void* sq, uint32_t Q, float R2, float* worst0,
+                                   hipStream_t st) {
+    const dim3 grid((Q + 255) / 256), block(256);
+    switch (D) {
+        case 2: hipLaunchKernelGGL(radius_to_worst0<2>, grid, block, 0, st, r0, (const NodeRec<2>*)sq, Q, R2, worst0); break;
+        case 3: hipLaunchKernelGGL(radius_to_worst0<3>, grid, block, 0, st, r0, (const NodeRec<3>*)sq, Q, R2, worst0); break;
+        default: hipLaunchKernelGGL(radius_to_worst0<4>, grid, block, 0, st, r0, (const NodeRec<4>*)sq, Q, R2, worst0); break;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
+
+size_t batch_rec_bytes() { return sizeof(BRec); }
+
+// One (dim, K) class of a batched call: gather into class records, zero the
+// range cursors, one persistent traversal launch.
+kd_status run_batch_class(const BatchJob* d_jobs, int njobs, int dim, int K, uint32_t n, const uint32_t* perm,
+                          void* recs, uint32_t* counters, const QueryPlan& plan, int device, hipStream_t st) {
+    if (n == 0) return KD_OK;
+    const DeviceInfo& dev = device_info(device);
+    const dim3 g((n + 255) / 256), b(256);
+    switch (dim) {
+        case 2: hipLaunchKernelGGL(batch_gather<2>, g, b, 0, st, d_jobs, njobs, perm, n, (BRec*)recs); break;
+        case 3: hipLaunchKernelGGL(batch_gather<3>, g, b, 0, st, d_jobs, njobs, perm, n, (BRec*)recs); break;
+        default: hipLaunchKernelGGL(batch_gather<4>, g, b, 0, st, d_jobs, njobs, perm, n, (BRec*)recs); break;
+    }
+    KD_HIP(hipGetLastError());
+    int block = plan.block;
+    if (K >= 32 && block > 256) block = 256;
+    int occ = 0;
+    hipError_t e = dim == 2 ? occupancy_batched_k<2>(K, block, &occ)
+                 : dim == 3 ? occupancy_batched_k<3>(K, block, &occ) : occupancy_batched_k<4>(K, block, &occ);
+    if (e != hipSuccess) return hip_error(e, "occupancy query");
+    int64_t per_cu = plan.waves_per_cu / (block / 64);
+    if (per_cu < 1) per_cu = 1;
+    if (occ > 0 && per_cu > occ) per_cu = occ;
+    int64_t grid = int64_t(dev.cus) * per_cu;
+    const int64_t need = (int64_t(n) + block - 1) / block;
+    if (grid > need) grid = need;
+    if (grid > 8 && grid % 8) grid -= grid % 8;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(zero_u32, dim3(unsigned((grid + 255) / 256)), dim3(256), 0, st, counters, int(grid));
+    KD_HIP(hipGetLastError());
+    BatchArgs a{d_jobs, reinterpret_cast<const BRec*>(recs), n, counters};
+    e = dim == 2 ? dispatch_batched_k<2>(K, a, block, int(grid), st)
+      : dim == 3 ? dispatch_batched_k<3>(K, a, block, int(grid), st) : dispatch_batched_k<4>(K, a, block, int(grid), st);
+    if (e != hipSuccess) return hip_error(e, "knn_batched launch");
+    return KD_OK;
+}
 
 int k_template(int k) {
     int K = 1;
@@ -502,19 +850,28 @@ int k_template(int k) {
     return K;
 }
 
-kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan,
-                  int32_t* out_idx, float* out_d2, uint32_t* visited, kd_stream stream) {
+kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan, int32_t* out_idx,
+                  float* out_d2, uint32_t* visited, kd_stream stream, const LearnedSpec* learned,
+                  uint32_t* fallbacks_out) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const DeviceInfo& dev = device_info(t->device);
     void* ws = nullptr;
-    const size_t head = 64 * 1024;  // range cursors
+    // scratch: [cursors pass 1 | cursors pass 2 | fallback count] queries  sort  worst0  fallback list
+    const size_t head = 72 * 1024;
     const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
     const size_t sort_bytes = plan.sort_bits > 0 ? sort_scratch_bytes(Q) : 0;
-    kd_status s = scratch(stream, head + sq_bytes + sort_bytes, &ws);
+    const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
+    const size_t learn_bytes = learned ? 2 * q4 : 0;
+    kd_status s = scratch(stream, head + sq_bytes + sort_bytes + learn_bytes, &ws);
     if (s != KD_OK) return s;
-    uint32_t* counter = reinterpret_cast<uint32_t*>(ws);
-    void* sq = static_cast<char*>(ws) + head;
-    void* sort_ws = static_cast<char*>(ws) + head + sq_bytes;
+    char* base = static_cast<char*>(ws);
+    uint32_t* counter1 = reinterpret_cast<uint32_t*>(base);
+    uint32_t* counter2 = reinterpret_cast<uint32_t*>(base + 32 * 1024);
+    uint32_t* fb_count = reinterpret_cast<uint32_t*>(base + 64 * 1024);
+    void* sq = base + head;
+    void* sort_ws = base + head + sq_bytes;
+    float* worst0 = learned ? reinterpret_cast<float*>(base + head + sq_bytes + sort_bytes) : nullptr;
+    uint32_t* fb_list = learned ? reinterpret_cast<uint32_t*>(base + head + sq_bytes + sort_bytes + q4) : nullptr;
 
     // query reorder: Morton sort, then gather into traversal order
     const uint32_t* perm = nullptr;
@@ -528,7 +885,21 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     s = timing_end(st, evs, "sort");
     if (s != KD_OK) return s;
 
-    TravArgs a;
+    if (learned) {
+        hipEvent_t evm;
+        s = timing_begin(st, &evm);
+        if (s != KD_OK) return s;
+        if (learned->params)
+            e = launch_mlp_worst0(learned->params, learned->lo, learned->inv, learned->margin, plan.R2, sq,
+                                  uint32_t(Q), worst0, st);
+        else
+            e = launch_radius_to_worst0(t->dim, learned->r0, sq, uint32_t(Q), plan.R2, worst0, st);
+        if (e != hipSuccess) return hip_error(e, "initial radius launch");
+        s = timing_end(st, evm, "mlp");
+        if (s != KD_OK) return s;
+    }
+
+    TravArgs a = {};
     a.nodes = t->d_nodes;
     a.N = int32_t(t->N);
     a.sq = sq;
@@ -538,9 +909,15 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     a.out_idx = out_idx;
     a.out_d2 = out_d2;
     a.visited = visited;
-    a.counter = counter;
+    a.counter = counter1;
     a.vec_store = (plan.k % 4 == 0) && (reinterpret_cast<uintptr_t>(out_idx) % 16 == 0) &&
                   (reinterpret_cast<uintptr_t>(out_d2) % 16 == 0);
+    if (learned) {
+        a.worst0 = worst0;
+        a.fb_list = fb_list;
+        a.fb_count = fb_count;
+        a.fb_flag = learned->fb_flag;
+    }
 
     int block = plan.block;
     if (plan.K >= 32 && block > 256) block = 256;
@@ -556,14 +933,41 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     if (grid > need) grid = need;
     if (grid > 8 && grid % 8) grid -= grid % 8;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(zero_u32, dim3(unsigned((grid + 255) / 256)), dim3(256), 0, st, counter, int(grid));
+    // zero both cursor sets and the fallback count
+    hipLaunchKernelGGL(zero_u32, dim3(unsigned((16 * 1024 + 1 + 255) / 256)), dim3(256), 0, st, counter1,
+                       16 * 1024 + 1);
     KD_HIP(hipGetLastError());
     hipEvent_t ev0;
     s = timing_begin(st, &ev0);
     if (s != KD_OK) return s;
-    e = dispatch_dk(t->dim, plan.K, a, block, int(grid), st);
+    e = dispatch_dk(t->dim, plan.K, a, learned != nullptr, block, int(grid), st);
     if (e != hipSuccess) return hip_error(e, "knn_persistent launch");
-    return timing_end(st, ev0, "traverse");
+    s = timing_end(st, ev0, "traverse");
+    if (s != KD_OK) return s;
+    if (!learned) return KD_OK;
+
+    // second pass: the fallback slots, plain traversal from R2
+    TravArgs b = a;
+    b.worst0 = nullptr;
+    b.fb_list = nullptr;
+    b.fb_count = nullptr;
+    b.fb_flag = nullptr;
+    b.slot_list = fb_list;
+    b.slot_count = fb_count;
+    b.visited_add = 1;
+    b.counter = counter2;
+    hipEvent_t ev1;
+    s = timing_begin(st, &ev1);
+    if (s != KD_OK) return s;
+    e = dispatch_dk(t->dim, plan.K, b, false, block, int(grid), st);
+    if (e != hipSuccess) return hip_error(e, "fallback pass launch");
+    s = timing_end(st, ev1, "fallback");
+    if (s != KD_OK) return s;
+    if (fallbacks_out) {
+        KD_HIP(hipMemcpyAsync(fallbacks_out, fb_count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        KD_HIP(hipStreamSynchronize(st));
+    }
+    return KD_OK;
 }
 
 }  // namespace kd

@@ -1,0 +1,158 @@
+"""GPU tests of the learned initial radius: exactness of the two-pass rule for
+any radius (results byte-identical to the plain traversal and to the oracle,
+fallback set equal to the oracle's), the MLP kernels against the float64
+reference, on-GPU training, and what the trained network gains."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2210_12859_amd as kd  # noqa: E402
+from paper_2210_12859_amd import datagen  # noqa: E402
+from oracle import mlp_ref as M  # noqa: E402
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return torch.device("cuda:0")
+
+
+def _t(a, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype)).to(_dev())
+
+
+@pytest.fixture(scope="module")
+def c1(oracle_lib):
+    P, Qs = datagen.workload("uniform-16k")
+    tree = kd.kd_build(_t(P))
+    return P, Qs, tree, oracle_lib.build_tree(P)
+
+
+def _radii(Qs, pd, rng):
+    kth = np.sqrt(pd[:, -1].astype(np.float64))
+    n = len(Qs)
+    return {
+        "zero": np.zeros(n), "tiny": np.full(n, 1e-30), "negative": np.full(n, -1.0),
+        "nan": np.full(n, np.nan), "inf": np.full(n, np.inf), "random": rng.random(n) * 0.05,
+        "perfect": kth * (1 + 2.0 ** -20), "under": kth * 0.9, "mixed": np.where(rng.random(n) < 0.5, kth, 0.0),
+    }
+
+
+@pytest.mark.parametrize("k,maxr", [(1, math.inf), (8, math.inf), (8, 0.03), (13, math.inf), (64, math.inf)])
+def test_injected_radius_is_exact(c1, oracle_lib, k, maxr):
+    P, Qs, tree, order = c1
+    pi, pd, pv = oracle_lib.knn(P, order, Qs, k, maxr)
+    rng = np.random.default_rng(k)
+    for name, r0 in _radii(Qs, pd, rng).items():
+        r0 = r0.astype(np.float32)
+        print(f"[gpu] injected radius {name} k={k} maxr={maxr}", flush=True)
+        gi, gd, gv, gf = kd.kd_knn_with_radius(tree, _t(r0), _t(Qs), k, maxr, want_visited=True, want_flags=True)
+        torch.cuda.synchronize()
+        gi = gi.cpu().numpy().reshape(-1, k)
+        gd = gd.cpu().numpy().reshape(-1, k)
+        assert np.array_equal(gi, pi), name
+        assert np.array_equal(gd.view(np.uint32), pd.view(np.uint32)), name
+        li, ld, lv, lfb = oracle_lib.knn_learned(P, order, Qs, k, r0, maxr)
+        assert np.array_equal(gf.cpu().numpy().astype(bool), lfb), name
+
+
+def test_mlp_forward_matches_reference():
+    rng = np.random.default_rng(3)
+    theta = (M.he_init(11) + 0.05 * rng.standard_normal(M.NPARAM)).astype(np.float32)
+    lo = np.array([0.1, -0.2, 0.0], np.float32)
+    inv = np.array([1.0, 0.5, 2.0], np.float32)
+    model = kd.kd_model_create(theta, lo, inv, 0.0, 8)
+    q = rng.random((5000, 3), dtype=np.float32)
+    y = kd.kd_mlp_predict(model, _t(q)).cpu().numpy().astype(np.float64)
+    yr, _ = M.forward(theta.astype(np.float64), M.normalize(q, lo, inv))
+    err = np.abs(y - yr)
+    tol = 1 + np.abs(yr)
+    # float32 accumulation differs from float64 by a few ulp; a bfloat16
+    # activation that lands on the other side of a rounding boundary moves y
+    # by about one bfloat16 ulp of one term (<~ 2^-8 relative)
+    assert np.quantile(err / tol, 0.95) < 1e-4, np.quantile(err / tol, 0.95)
+    assert (err / tol).max() < 2e-2, (err / tol).max()
+
+
+def test_mlp_gradient_matches_reference():
+    rng = np.random.default_rng(4)
+    theta = (M.he_init(12) + 0.05 * rng.standard_normal(M.NPARAM)).astype(np.float32)
+    lo = np.zeros(3, np.float32)
+    inv = np.ones(3, np.float32)
+    model = kd.kd_model_create(theta, lo, inv, 0.0, 8)
+    n = 1000
+    q = rng.random((n, 3), dtype=np.float32)
+    t = (rng.standard_normal(n) * 0.3 - 4.0).astype(np.float32)
+    loss, g = kd.kd_mlp_grad(model, _t(q), _t(t))
+    lr, gr = M.backward(theta.astype(np.float64), M.normalize(q, lo, inv), t.astype(np.float64))
+    assert abs(loss - lr) <= 1e-4 * abs(lr)
+    g = g.astype(np.float64)
+    o = 0
+    for name, shape in M.SIZES:
+        m = int(np.prod(shape))
+        a, b = g[o:o + m], gr[o:o + m]
+        o += m
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        print(f"[gpu] grad {name}: rel err {rel:.2e}", flush=True)
+        assert rel < 2e-2, (name, rel)
+    assert np.linalg.norm(g - gr) / np.linalg.norm(gr) < 1e-2
+
+
+def test_train_and_learned_query_exact(oracle_lib, tmp_path):
+    P = datagen.uniform(1 << 16, 3, 0)
+    train = datagen.uniform(1 << 16, 3, 5)
+    Qs = datagen.uniform(20000, 3, 6)
+    tree = kd.kd_build(_t(P))
+    print("[gpu] training", flush=True)
+    model = kd.kd_radius_model_train(tree, _t(train), 8, epochs=12, batch=1024, seed=1)
+    info = model.info()
+    assert len(info["loss_curve"]) == 12
+    assert info["loss_curve"][-1] < info["loss_curve"][0]
+    # labels on the held-out tail vary; the model must explain part of it
+    order = oracle_lib.build_tree(P)
+    _, d_hold, _ = oracle_lib.knn(P, order, train[-6553:], 8)
+    assert info["holdout_rmse"] < np.std(M.label(d_hold[:, -1]))
+    gi, gd, gv, st = kd.kd_knn_learned(tree, model, _t(Qs), 8, want_visited=True, want_stats=True)
+    torch.cuda.synchronize()
+    pi, pd, pv = oracle_lib.knn(P, order, Qs, 8)
+    assert np.array_equal(gi.cpu().numpy(), pi)
+    assert np.array_equal(gd.cpu().numpy().view(np.uint32), pd.view(np.uint32))
+    assert st["queries"] == len(Qs)
+    assert st["fallbacks"] < 0.2 * len(Qs)
+    # save / load round trip
+    path = os.path.join(str(tmp_path), "m.kdm")
+    model.save(path)
+    m2 = kd.kd_model_load(path)
+    p1, lo1, inv1 = model.params()
+    p2, lo2, inv2 = m2.params()
+    assert np.array_equal(p1, p2) and np.array_equal(lo1, lo2) and m2.info()["margin"] == info["margin"]
+    gi2, _, _, _ = kd.kd_knn_learned(tree, m2, _t(Qs), 8)
+    torch.cuda.synchronize()
+    assert np.array_equal(gi2.cpu().numpy(), pi)
+
+
+def test_learned_gain_report(oracle_lib):
+    """What the trained network gains: processed nodes and time of plain vs
+    learned vs constant radius vs perfect radius on 1M uniform points, k=8.
+    Results are asserted identical; the gain is reported, not asserted."""
+    P, Qs = datagen.workload("uniform-1m")
+    train = datagen.uniform(1 << 20, 3, 7)
+    tree = kd.kd_build(_t(P))
+    q = _t(Qs)
+    model = kd.kd_radius_model_train(tree, _t(train), 8, epochs=4, batch=8192, seed=2)
+    pi, pd, pv = kd.kd_knn_ex(tree, q, 8, want_visited=True)
+    li, ld, lv, st = kd.kd_knn_learned(tree, model, q, 8, want_visited=True, want_stats=True)
+    kth = torch.sqrt(pd[:, -1].double()).float()
+    ci, cd, cv, _ = kd.kd_knn_with_radius(tree, torch.full_like(kth, float(torch.quantile(kth, 0.95))), q, 8,
+                                          want_visited=True)
+    fi, fd, fv, _ = kd.kd_knn_with_radius(tree, kth * (1 + 2 ** -20), q, 8, want_visited=True)
+    torch.cuda.synchronize()
+    for a, b in [(li, pi), (ci, pi), (fi, pi)]:
+        assert torch.equal(a, b)
+    tot = lambda v: int(v.to(torch.int64).sum().item())
+    print(f"[gpu] processed nodes: plain {tot(pv)} learned {tot(lv)} constant {tot(cv)} perfect {tot(fv)}; "
+          f"fallbacks {st['fallbacks']}", flush=True)
