@@ -87,6 +87,56 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_calibration_bytes": nbytes, "launches": reps}), flush=True)
 
 
+def bench_learned(kd, datagen, tree, q, oi, od, k, args, plain_visited, plain_ms):
+    """Learned initial radius on the same queries: train (untimed) on separate
+    queries of the same distribution, then time kd_knn_learned like the plain
+    step.  Results are checked identical to the plain results."""
+    import torch
+    dev = q.device
+    train = torch.from_numpy(datagen.uniform(1 << 20, q.shape[1], 7)).to(dev)
+    t0 = time.perf_counter()
+    model = kd.kd_radius_model_train(tree, train, k, epochs=args.train_epochs, batch=8192, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    info = model.info()
+    log(f"learned: trained in {train_s:.2f}s, holdout rmse {info['holdout_rmse']:.3f}, margin {info['margin']:.3f}")
+    li = torch.empty_like(oi)
+    ld = torch.empty_like(od)
+    vis = torch.empty(q.shape[0], dtype=torch.int32, device=dev)
+    _, _, _, st = kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld, visited=vis, want_stats=True)
+    torch.cuda.synchronize()
+    identical = bool(torch.equal(li, oi) and torch.equal(ld.view(torch.int32), od.view(torch.int32)))
+    lvis = int(vis.to(torch.int64).sum().item())
+    for _ in range(args.warmup):
+        kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld)
+    torch.cuda.synchronize()
+    kd.kd_timing_enable(True)
+    for name in ("sort", "mlp", "traverse", "fallback"):
+        kd.kd_timing_collect(name)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    stages = {}
+    for name in ("sort", "mlp", "traverse", "fallback"):
+        tot, n = kd.kd_timing_collect(name)
+        stages[name + "_ms"] = tot / max(1, n)
+    kd.kd_timing_enable(False)
+    model.close()
+    value = q.shape[0] / (ms / 1e3)
+    log(f"learned: {ms:.3f} ms/step, {value / 1e6:.1f} M queries/s ({plain_ms / ms:.3f}x plain), "
+        f"fallbacks {st['fallbacks']}, identical {identical}")
+    return {"value": value, "unit": "queries/s", "ms_per_step": ms, "speedup_vs_plain": plain_ms / ms,
+            "identical_to_plain": identical, "fallbacks": st["fallbacks"], "visited_per_query": lvis / q.shape[0],
+            "visited_ratio_vs_plain": lvis / plain_visited, "train_s": train_s, "train_queries": int(train.shape[0]),
+            "epochs": args.train_epochs, "holdout_rmse": info["holdout_rmse"], "margin": info["margin"], **stages}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +145,8 @@ def main():
     ap.add_argument("--workload", default="uniform-1m", choices=sorted(WORKLOADS))
     ap.add_argument("--k", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-radius variant")
+    ap.add_argument("--train-epochs", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -184,6 +236,8 @@ def main():
         "visited_per_query": visited_total / Q,
         "nodes_visited_per_s": visited_total / (ms_per_step / 1e3),
     }
+    if not args.no_learned and D == 3:
+        out["learned"] = bench_learned(kd, datagen, tree, q, oi, od, k, args, visited_total, ms_per_step)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(P, Qs, k)

@@ -132,9 +132,8 @@ kd_status kd_knn_ex(kd_tree t, const float* queries, int64_t Q, int k, float max
  * neighbour) for each query.  A learned query starts its traversal from the
  * squared radius worst0 = min(R2, fl32(r0 * r0)), r0 = exp(y + margin), in
  * place of R2 (the search radius of Sec. 3 may start at any value that
- * contains the answer), and skips the descent through nodes whose splitting
- * plane lies outside worst0.  Every query that finds fewer than k points
- * within worst0 < R2 is run again from R2.  Results are therefore
+ * contains the answer).  A query that finds fewer than k points within
+ * worst0 < R2 restarts, in the same lane, from R2.  Results are therefore
  * byte-identical to kd_knn for ANY model: the model changes speed only.
  * The model is 3-D (trees of dim 3). */
 
@@ -164,13 +163,13 @@ kd_status kd_radius_model_train(kd_tree t, const float* train_q, int64_t Qt, int
                                 kd_model* out, kd_stream stream);
 
 /* kd_knn with the model's initial radius (see above).  visited (nullable,
- * device uint32 [Q]) counts processed nodes of both passes; stats (nullable,
+ * device uint32 [Q]) counts processed nodes of both runs; stats (nullable,
  * HOST) receives the fallback count, which synchronises the stream. */
 kd_status kd_knn_learned(kd_tree t, kd_model m, const float* queries, int64_t Q, int k, float maxRadius,
                          int32_t* out_idx, float* out_d2, uint32_t* visited, kd_stats* stats, const kd_opts* opts,
                          kd_stream stream);
 
-/* The same two-pass query with caller radii: r0 is device float32 [Q] in
+/* The same query with caller radii: r0 is device float32 [Q] in
  * caller order (any value: NaN, negative or +inf means "no initial radius").
  * fell_back (nullable, device uint8 [Q]) receives 1 for queries re-run from
  * R2.  For checking the exact-fallback rule with arbitrary radii. */

@@ -3,7 +3,7 @@
 //
 // The model predicts y ~ ln(distance to the k-th neighbour) per query; the
 // query path starts each traversal from worst0 = min(R2, fl(exp(y+m)^2)) and
-// re-runs, from R2, every query that found fewer than k points inside
+// restarts, from R2, every query that found fewer than k points inside
 // worst0.  Results are therefore identical to the plain traversal for any
 // model; the model only affects speed.
 #include <hip/hip_runtime.h>

@@ -64,15 +64,10 @@ struct TravArgs {
     uint32_t* visited;       // [Q] or NULL
     uint32_t* counter;       // [gridDim.x] per-workgroup range cursors, zero at launch
     int vec_store;           // outputs 16-byte aligned with k % 4 == 0: vector stores
-    // learned-radius pass
-    const float* worst0;     // [Q] initial squared radius per slot (learned kernels)
-    uint32_t* fb_list;       // slots whose learned pass found < k points (learned kernels)
-    uint32_t* fb_count;
-    uint8_t* fb_flag;        // [Q] caller order, 1 = fell back (nullable)
-    // indirect pass: query slots are slot_list[0 .. *slot_count)
-    const uint32_t* slot_list;
-    const uint32_t* slot_count;
-    int visited_add;         // add to visited[] instead of storing
+    // learned-radius kernels
+    const float* worst0;     // [Q] initial squared radius per slot
+    uint32_t* fb_count;      // queries restarted from R2 (nullable)
+    uint8_t* fb_flag;        // [Q] caller order, 1 = restarted from R2 (nullable)
 };
 
 __device__ __forceinline__ uint64_t make_key(float d2, int32_t idx) {
@@ -162,60 +157,53 @@ __device__ __forceinline__ NodeRec<D> shfl_rec(const NodeRec<D>& r, int src) {
 // the split dimension of `curr` (implied by its level, tracked as the lane
 // moves), the query and its k-best list.
 //
-// Learned-radius lanes start from worst0 <= R2 instead of R2.  They first
-// descend from the root along close children while the splitting plane is
-// farther than the radius (sd^2 > worst0): such a node's point has
-// d2 >= sd^2 > worst0 and its far subtree is farther still, so neither can
-// enter the list; the traversal proper then starts at the first node whose
-// plane is within range, and ends when it returns to that node's parent
-// (`stop`).  Plain lanes have stop = 0, the root's parent.
+// Learned-radius lanes start from the squared radius worst0 <= R2 instead
+// of R2 (the list's sentinel entries carry worst0).  A lane that ends with
+// fewer than k points found inside worst0 < R2 restarts in place from R2, so
+// every result equals the plain traversal's.
 template <int D, int K>
 struct Lane {
     float q[D];
     uint64_t L[K];
     int32_t curr, prev;
-    int32_t stop;      // returning to this id ends the traversal
     int32_t row;
-    uint32_t slot;
     uint32_t vis;
-    float w0;          // initial squared radius
-    bool skipping;     // still in the learned start-node descent
+    float w0;          // initial squared radius of the current run
+    bool fell_back;    // the learned run found < k points and was restarted
 };
 
+template <int D, int K>
+__device__ __forceinline__ void lane_reset(Lane<D, K>& s, int k, float w0) {
+    s.w0 = w0;
+    // Slots beyond k hold the smallest key so the list's worst entry is the
+    // k-th real one; real keys are >= 0 and never move in front of them.
+    const uint64_t sent = make_key(w0, SENT_IDX);
+#pragma unroll
+    for (int j = 0; j < K; ++j) s.L[j] = (j < K - k) ? uint64_t(0) : sent;
+    s.curr = 1;   // root
+    s.prev = 0;   // the root's parent
+}
+
 template <int D, int K, bool LEARNED>
-__device__ __forceinline__ void lane_start(Lane<D, K>& s, const TravArgs& a, const NodeRec<D>& qr, uint32_t slot,
-                                           float w0) {
+__device__ __forceinline__ void lane_start(Lane<D, K>& s, const TravArgs& a, const NodeRec<D>& qr, float w0) {
 #pragma unroll
     for (int j = 0; j < D; ++j) s.q[j] = qr.c[j];
     s.row = qr.idx;
-    s.slot = slot;
-    s.w0 = LEARNED ? w0 : a.R2;
-    // Slots beyond k hold the smallest key so the list's worst entry is the
-    // k-th real one; real keys are >= 0 and never move in front of them.
-    const uint64_t sent = make_key(s.w0, SENT_IDX);
-#pragma unroll
-    for (int j = 0; j < K; ++j) s.L[j] = (j < K - a.k) ? uint64_t(0) : sent;
-    s.curr = 1;   // root
-    s.prev = 0;   // the root's parent
-    s.stop = 0;
     s.vis = 0;
-    s.skipping = LEARNED;
+    s.fell_back = false;
+    lane_reset<D, K>(s, a.k, LEARNED ? w0 : a.R2);
+}
+
+// A finished learned run with fewer than k points inside worst0 < R2: its
+// list may miss points beyond worst0, so the query runs again from R2.
+template <int D, int K>
+__device__ __forceinline__ bool lane_needs_restart(const Lane<D, K>& s, float R2) {
+    return uint32_t(s.L[K - 1]) == SENT_IDX && s.w0 < R2;
 }
 
 template <int D, int K, bool LEARNED>
 __device__ __forceinline__ void lane_finish(const Lane<D, K>& s, const TravArgs& a) {
-    if (LEARNED) {
-        // fewer than k points within worst0 < R2: the result may be
-        // incomplete, so the query is re-run from R2 in the second pass
-        const bool fell_back = uint32_t(s.L[K - 1]) == SENT_IDX && s.w0 < a.R2;
-        if (a.fb_flag) a.fb_flag[s.row] = fell_back ? 1 : 0;
-        if (fell_back) {
-            const uint32_t pos = atomicAdd(a.fb_count, 1u);
-            a.fb_list[pos] = s.slot;
-            if (a.visited) a.visited[s.row] = s.vis;
-            return;
-        }
-    }
+    if (LEARNED && a.fb_flag) a.fb_flag[s.row] = s.fell_back ? 1 : 0;
     int32_t* oi = a.out_idx + int64_t(s.row) * a.k;
     float* od = a.out_d2 ? a.out_d2 + int64_t(s.row) * a.k : nullptr;
     const int off = K - a.k;
@@ -249,16 +237,13 @@ __device__ __forceinline__ void lane_finish(const Lane<D, K>& s, const TravArgs&
             }
         }
     }
-    if (a.visited) {
-        if (a.visited_add) a.visited[s.row] += s.vis;
-        else a.visited[s.row] = s.vis;
-    }
+    if (a.visited) a.visited[s.row] = s.vis;
 }
 
 // One loop trip for a lane at node s.curr (record fields c, idx, anc):
 // the state-machine step at curr, then up to F fused "return to parent"
 // steps.  Returns the new curr (0 = traversal finished).
-template <int D, int K, int F, bool LEARNED>
+template <int D, int K, int F>
 __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D], int32_t idx,
                                              const float (&anc)[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1],
                                              int32_t N) {
@@ -268,19 +253,6 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
 #pragma unroll
     for (int j = 0; j < D; ++j) dx[j] = s.q[j] - c[j];
     const float sd = sel_rot<D>(dx, dim, 0);
-    if (LEARNED && s.skipping) {
-        if (sd * sd > s.w0) {
-            // skip: node and far subtree are out of range; follow the close child
-            const int32_t close_c = (curr << 1) | (sd > 0.0f ? 1 : 0);
-            const int32_t next = close_c <= N ? close_c : s.stop;  // nothing in range: finish
-            s.prev = curr;
-            s.curr = next;
-            return next;
-        }
-        s.skipping = false;
-        s.stop = curr >> 1;  // the traversal proper starts here (prev < curr)
-    }
-
     const bool from_parent = s.prev < curr;
     // processNode on the first visit: exact binary32 squared distance, left
     // to right (computed branch-free; only the insertion is conditional).
@@ -311,7 +283,7 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     // keep returning.
 #pragma unroll
     for (int i = 0; i < F; ++i) {
-        const bool live = up & (anc_id != s.stop);
+        const bool live = up & (anc_id != 0);
         if (__any(live)) {
             if (live) {
                 const float sda = sel_rot<D>(s.q, dim, i + 1) - anc[i];
@@ -330,7 +302,7 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
         }
     }
     if (up) {
-        next = anc_id;  // == stop once the start node has returned: finished
+        next = anc_id;  // 0 once the root has returned: finished
         nprev = child;
     }
     s.prev = nprev;
@@ -395,16 +367,14 @@ template <int D, int K, int F, bool LEARNED>
 __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
     const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes) - 1;  // 1-based
     const NodeRec<D>* __restrict__ sq = reinterpret_cast<const NodeRec<D>*>(a.sq);
-    if (a.slot_count) a.Q = *a.slot_count;  // indirect pass: count produced on the device
 
     const uint32_t lane = __lane_id();
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
     WorkSource ws{group_range(blockIdx.x, gridDim.x), gridDim.x, 0u, 64u, blockDim.x >> 6, false};
     // Query chunk held across the wave: lane l holds slot cb + l of the
-    // current chunk (record, slot index, initial radius); idle lanes take
-    // queries from it by cross-lane shuffle.
+    // current chunk (record and, when learned, initial radius); idle lanes
+    // take queries from it by cross-lane shuffle.
     NodeRec<D> chunk;
-    uint32_t chunk_slot = 0;
     float chunk_w0 = 0.0f;
     uint32_t cpos = 0, cn = 0;
 
@@ -419,10 +389,9 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
             {
                 const int src = int(cpos + (rank < take1 ? rank : 0));
                 const NodeRec<D> v = shfl_rec<D>(chunk, src);
-                const uint32_t vs = __shfl(chunk_slot, src);
                 const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
                 if (!active && rank < take1) {
-                    lane_start<D, K, LEARNED>(s, a, v, vs, vw);
+                    lane_start<D, K, LEARNED>(s, a, v, vw);
                     active = true;
                 }
             }
@@ -432,20 +401,17 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
                 ws.grab(a, lane, cb, cn2);
                 if (cn2) {
                     if (lane < cn2) {
-                        const uint32_t i = cb + lane;
-                        chunk_slot = a.slot_list ? a.slot_list[i] : i;
-                        chunk = load_query<D>(sq + chunk_slot);
-                        if (LEARNED) chunk_w0 = a.worst0[chunk_slot];
+                        chunk = load_query<D>(sq + cb + lane);
+                        if (LEARNED) chunk_w0 = a.worst0[cb + lane];
                     }
                     cn = cn2;
                     const uint32_t r2 = rank - take1;
                     const uint32_t take2 = n - take1 < cn2 ? n - take1 : cn2;
                     const int src = int(r2 < take2 ? r2 : 0);
                     const NodeRec<D> v = shfl_rec<D>(chunk, src);
-                    const uint32_t vs = __shfl(chunk_slot, src);
                     const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
                     if (!active && rank >= take1 && r2 < take2) {
-                        lane_start<D, K, LEARNED>(s, a, v, vs, vw);
+                        lane_start<D, K, LEARNED>(s, a, v, vw);
                         active = true;
                     }
                     cpos = take2;
@@ -461,10 +427,16 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
             int32_t idx;
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
             load_tree<D>(g1 + s.curr, c, idx, anc);
-            const int32_t next = lane_step<D, K, F, LEARNED>(s, c, idx, anc, a.N);
-            if (next == s.stop) {
-                lane_finish<D, K, LEARNED>(s, a);
-                active = false;
+            const int32_t next = lane_step<D, K, F>(s, c, idx, anc, a.N);
+            if (next == 0) {
+                if (LEARNED && lane_needs_restart<D, K>(s, a.R2)) {
+                    s.fell_back = true;
+                    if (a.fb_count) atomicAdd(a.fb_count, 1u);
+                    lane_reset<D, K>(s, a.k, a.R2);
+                } else {
+                    lane_finish<D, K, LEARNED>(s, a);
+                    active = false;
+                }
             }
         }
     }
@@ -632,16 +604,9 @@ __device__ __forceinline__ void batch_start(Lane<D, K>& s, JobLane<D, K>& j, con
 #pragma unroll
     for (int d = 0; d < D; ++d) s.q[d] = r.c[d];
     s.row = r.row;
-    s.slot = 0;
-    s.w0 = J.R2;
-    const uint64_t sent = make_key(J.R2, SENT_IDX);
-#pragma unroll
-    for (int e = 0; e < K; ++e) s.L[e] = (e < K - j.k) ? uint64_t(0) : sent;
-    s.curr = 1;
-    s.prev = 0;
-    s.stop = 0;
     s.vis = 0;
-    s.skipping = false;
+    s.fell_back = false;
+    lane_reset<D, K>(s, j.k, J.R2);
 }
 
 template <int D, int K>
@@ -738,8 +703,8 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
             int32_t idx;
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
             load_tree<D>(j.g1 + s.curr, c, idx, anc);
-            const int32_t next = lane_step<D, K, F, false>(s, c, idx, anc, j.N);
-            if (next == s.stop) {
+            const int32_t next = lane_step<D, K, F>(s, c, idx, anc, j.N);
+            if (next == 0) {
                 batch_finish<D, K>(s, j);
                 active = false;
             }
@@ -856,22 +821,20 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const DeviceInfo& dev = device_info(t->device);
     void* ws = nullptr;
-    // scratch: [cursors pass 1 | cursors pass 2 | fallback count] queries  sort  worst0  fallback list
+    // scratch: [range cursors | restart count] queries  sort  worst0
     const size_t head = 72 * 1024;
     const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
     const size_t sort_bytes = plan.sort_bits > 0 ? sort_scratch_bytes(Q) : 0;
     const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
-    const size_t learn_bytes = learned ? 2 * q4 : 0;
+    const size_t learn_bytes = learned ? q4 : 0;
     kd_status s = scratch(stream, head + sq_bytes + sort_bytes + learn_bytes, &ws);
     if (s != KD_OK) return s;
     char* base = static_cast<char*>(ws);
     uint32_t* counter1 = reinterpret_cast<uint32_t*>(base);
-    uint32_t* counter2 = reinterpret_cast<uint32_t*>(base + 32 * 1024);
     uint32_t* fb_count = reinterpret_cast<uint32_t*>(base + 64 * 1024);
     void* sq = base + head;
     void* sort_ws = base + head + sq_bytes;
     float* worst0 = learned ? reinterpret_cast<float*>(base + head + sq_bytes + sort_bytes) : nullptr;
-    uint32_t* fb_list = learned ? reinterpret_cast<uint32_t*>(base + head + sq_bytes + sort_bytes + q4) : nullptr;
 
     // query reorder: Morton sort, then gather into traversal order
     const uint32_t* perm = nullptr;
@@ -914,7 +877,6 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
                   (reinterpret_cast<uintptr_t>(out_d2) % 16 == 0);
     if (learned) {
         a.worst0 = worst0;
-        a.fb_list = fb_list;
         a.fb_count = fb_count;
         a.fb_flag = learned->fb_flag;
     }
@@ -933,7 +895,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     if (grid > need) grid = need;
     if (grid > 8 && grid % 8) grid -= grid % 8;
     if (grid < 1) grid = 1;
-    // zero both cursor sets and the fallback count
+    // zero the cursors and the restart count
     hipLaunchKernelGGL(zero_u32, dim3(unsigned((16 * 1024 + 1 + 255) / 256)), dim3(256), 0, st, counter1,
                        16 * 1024 + 1);
     KD_HIP(hipGetLastError());
@@ -943,25 +905,6 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     e = dispatch_dk(t->dim, plan.K, a, learned != nullptr, block, int(grid), st);
     if (e != hipSuccess) return hip_error(e, "knn_persistent launch");
     s = timing_end(st, ev0, "traverse");
-    if (s != KD_OK) return s;
-    if (!learned) return KD_OK;
-
-    // second pass: the fallback slots, plain traversal from R2
-    TravArgs b = a;
-    b.worst0 = nullptr;
-    b.fb_list = nullptr;
-    b.fb_count = nullptr;
-    b.fb_flag = nullptr;
-    b.slot_list = fb_list;
-    b.slot_count = fb_count;
-    b.visited_add = 1;
-    b.counter = counter2;
-    hipEvent_t ev1;
-    s = timing_begin(st, &ev1);
-    if (s != KD_OK) return s;
-    e = dispatch_dk(t->dim, plan.K, b, false, block, int(grid), st);
-    if (e != hipSuccess) return hip_error(e, "fallback pass launch");
-    s = timing_end(st, ev1, "fallback");
     if (s != KD_OK) return s;
     if (fallbacks_out) {
         KD_HIP(hipMemcpyAsync(fallbacks_out, fb_count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));

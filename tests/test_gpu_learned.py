@@ -1,4 +1,4 @@
-"""GPU tests of the learned initial radius: exactness of the two-pass rule for
+"""GPU tests of the learned initial radius: exactness of the restart rule for
 any radius (results byte-identical to the plain traversal and to the oracle,
 fallback set equal to the oracle's), the MLP kernels against the float64
 reference, on-GPU training, and what the trained network gains."""
