@@ -59,14 +59,17 @@ typedef enum {
 #define KD_MAX_POINTS (1LL << 30)
 
 /* Launch tuning.  Every setting gives byte-identical results; only speed
- * differs.  A zero-initialised struct, or NULL, means "tuned defaults"
- * (the autotuner's cached choice for the tree when kd_autotune ran). */
+ * differs.  Passing NULL means "the options kd_autotune chose for this tree
+ * and k, else the built-in defaults"; in a struct, a field at its "default"
+ * value below takes the built-in default. */
 typedef struct {
-    int block;       /* threads per workgroup: 64, 128, 256, 512 or 1024 (k > 16: at most 256); 0 = default */
-    int lds_levels;  /* top tree levels staged in LDS, 0..12; -1 = default */
+    int block;       /* threads per workgroup: 256, 512 or 1024 (k > 16: 256); 64, 128
+                        also accepted; 0 = default (256) */
+    int lds_levels;  /* reserved, ignored (0 or -1) */
     int sort_bits;   /* Morton bits the queries are sorted on before traversal:
-                        0 (no reordering), 8, 16, 24 or 32 (all bits); -1 = default */
-    int waves_per_cu;/* persistent grid size in waves per compute unit (capped by occupancy); 0 = default */
+                        0 (keep the caller's order), 8, 16, 24 or 32; -1 = default (16) */
+    int waves_per_cu;/* persistent grid size in waves per compute unit (capped by
+                        occupancy); 0 = default (24) */
 } kd_opts;
 
 /* ------------------------------------------------------------ tree build */
@@ -230,6 +233,21 @@ kd_status kd_batch_run(kd_batch b, kd_stream stream);
 kd_status kd_batch_free(kd_batch b);
 /* create + run + synchronise + free. */
 kd_status kd_knn_batched(const kd_job* jobs, int n_jobs, const kd_opts* opts, kd_stream stream);
+
+/* --------------------------------------------------------------- autotune */
+
+/* Times the candidate launch options (workgroup size 256/512/1024 x waves
+ * per CU 8..32 x Morton sort bits 0/16/24/32) on a sample of queries
+ * (device float32 [Qs][dim]) with the given k and maxRadius, keeps the
+ * fastest on the tree for k's list size, and returns it (best_out, best_ms
+ * are HOST and nullable).  Results never depend on the choice.
+ * Synchronises the stream. */
+kd_status kd_autotune(kd_tree t, const float* sample_q, int64_t Qs, int k, float maxRadius, kd_opts* best_out,
+                      float* best_ms, kd_stream stream);
+/* The options kept on the tree for k (KD_EINVAL if none), and setting them
+ * (for example from a cache file). */
+kd_status kd_tree_get_tuned(kd_tree t, int k, kd_opts* out);
+kd_status kd_tree_set_tuned(kd_tree t, int k, const kd_opts* opts);
 
 /* ------------------------------------------------------------ timing */
 

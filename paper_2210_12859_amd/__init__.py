@@ -85,6 +85,9 @@ def lib():
         "kd_batch_run": ([P, P], i32),
         "kd_batch_free": ([P], i32),
         "kd_knn_batched": ([P, i32, P, P], i32),
+        "kd_autotune": ([P, P, i64, i32, f32, P, P, P], i32),
+        "kd_tree_get_tuned": ([P, i32, P], i32),
+        "kd_tree_set_tuned": ([P, i32, P], i32),
         "kd_timing_enable": ([i32], i32),
         "kd_timing_collect": ([ctypes.c_char_p, P, P], i32),
         "kd_status_str": ([i32], ctypes.c_char_p),
@@ -437,6 +440,54 @@ class Batch:
 def kd_knn_batched(jobs, opts=None, stream=None):
     arr = _job_array(jobs)
     _check(lib().kd_knn_batched(arr, len(jobs), _opts(opts), _stream_handle(stream)))
+
+
+def _opts_dict(o: KdOpts):
+    return dict(block=o.block, lds_levels=o.lds_levels, sort_bits=o.sort_bits, waves_per_cu=o.waves_per_cu)
+
+
+def kd_autotune(tree: Tree, sample_q, k, max_radius=math.inf, stream=None):
+    """Tunes the launch options for (tree, k) on a sample; returns (opts dict, ms)."""
+    import torch
+    _require(sample_q, torch.float32, "sample_q")
+    o = KdOpts()
+    ms = ctypes.c_float()
+    _check(lib().kd_autotune(tree.handle, _ptr(sample_q), sample_q.shape[0], int(k), float(max_radius),
+                             ctypes.byref(o), ctypes.byref(ms), _stream_handle(stream)))
+    return _opts_dict(o), ms.value
+
+
+def kd_tree_get_tuned(tree: Tree, k):
+    o = KdOpts()
+    _check(lib().kd_tree_get_tuned(tree.handle, int(k), ctypes.byref(o)))
+    return _opts_dict(o)
+
+
+def kd_tree_set_tuned(tree: Tree, k, opts: dict):
+    o = KdOpts(opts.get("block", 0), opts.get("lds_levels", -1), opts.get("sort_bits", -1),
+               opts.get("waves_per_cu", 0))
+    _check(lib().kd_tree_set_tuned(tree.handle, int(k), ctypes.byref(o)))
+
+
+def save_tuning(tree: Tree, ks, path):
+    """Writes the tuned options of the given k values to a JSON cache file."""
+    import json
+    out = {}
+    for k in ks:
+        try:
+            out[str(k)] = kd_tree_get_tuned(tree, k)
+        except KdError:
+            pass
+    with open(path, "w") as f:
+        json.dump(out, f)
+
+
+def load_tuning(tree: Tree, path):
+    """Applies a JSON cache file written by save_tuning."""
+    import json
+    with open(path) as f:
+        for k, o in json.load(f).items():
+            kd_tree_set_tuned(tree, int(k), o)
 
 
 def kd_timing_enable(on: bool = True):

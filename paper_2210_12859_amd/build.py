@@ -31,6 +31,7 @@ SOURCES = [
     ("kd_mlp.hip", True),
     ("kd_model.cpp", True),
     ("kd_batch.cpp", True),
+    ("kd_autotune.cpp", True),
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",

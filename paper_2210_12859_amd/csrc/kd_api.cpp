@@ -202,7 +202,9 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     float r = maxRadius;
     p.R2 = r * r;  // binary32 product; +inf stays +inf
     kd_opts use{0, -1, -1, 0};
+    kd_opts tuned;
     if (o) use = *o;
+    else if (t && tuned_opts(t, p.K, &tuned)) use = tuned;
     if (use.block == 0) use.block = 256;
     if (use.lds_levels < 0) use.lds_levels = 0;
     if (use.sort_bits < 0) use.sort_bits = 16;

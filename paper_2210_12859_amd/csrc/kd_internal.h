@@ -79,6 +79,9 @@ int64_t left_subtree_size(int64_t n);
 // order[pos] = caller index; threads <= 0 picks the hardware count.
 void build_level_order(const float* pts, int64_t N, int dim, int32_t* order, int threads);
 
+// ---- tuned options (kd_autotune.cpp) ----------------------------------------
+bool tuned_opts(kd_tree t, int K, kd_opts* out);
+
 // ---- device info --------------------------------------------------------
 struct DeviceInfo {
     int cus = 256;

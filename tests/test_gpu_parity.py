@@ -190,3 +190,22 @@ def test_c2_full_scale(oracle_lib, wl):
         if len(rest):
             bi, bd = oracle_lib.brute(P, Qs[rest], k)
             assert np.array_equal(gi[rest], bi) and np.array_equal(gd[rest].view(np.uint32), bd.view(np.uint32))
+
+
+def test_autotune_choice_gives_identical_results(c1, oracle_lib, tmp_path):
+    P, Qs, tree, order = c1
+    q = torch.from_numpy(Qs).to(_dev())
+    opts, ms = kd.kd_autotune(tree, q, 8)
+    print(f"[gpu] autotune k=8: {opts} {ms:.3f} ms", flush=True)
+    assert ms > 0 and opts["block"] in (256, 512, 1024)
+    assert kd.kd_tree_get_tuned(tree, 8) == opts
+    gi, gd, gv = gpu_knn(tree, Qs, 8)  # default options now resolve to the tuned ones
+    oi, od, ov = oracle_lib.knn(P, order, Qs, 8)
+    assert_same(gi, gd, gv, oi, od, ov, "tuned")
+    path = str(tmp_path / "tune.json")
+    kd.save_tuning(tree, [8], path)
+    tree2 = build(P)
+    kd.load_tuning(tree2, path)
+    assert kd.kd_tree_get_tuned(tree2, 8) == opts
+    with pytest.raises(kd.KdError):
+        kd.kd_tree_get_tuned(tree2, 1)
