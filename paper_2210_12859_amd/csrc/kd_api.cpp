@@ -109,20 +109,25 @@ kd_status scratch(kd_stream stream, size_t bytes, void** out) {
 
 namespace {
 
+// Record of node id i (1-based, id = level-order position + 1) at array index
+// i; index 0 and index N + 1 are zero padding, so the two children of any node
+// (ids 2c, 2c + 1) sit in one aligned pair and a pair read never leaves the
+// allocation.
 template <int D>
 void pack_records(const float* pts, const int32_t* order, int64_t N, std::vector<unsigned char>& out) {
-    out.assign(size_t(N) * sizeof(TreeRec<D>), 0);
+    out.assign(size_t(N + 2) * sizeof(TreeRec<D>), 0);
     TreeRec<D>* r = reinterpret_cast<TreeRec<D>*>(out.data());
     for (int64_t pos = 0; pos < N; ++pos) {
+        TreeRec<D>& rec = r[pos + 1];
         const int32_t i = order[pos];
-        for (int j = 0; j < D; ++j) std::memcpy(&r[pos].w[j], &pts[int64_t(i) * D + j], 4);
-        r[pos].w[D] = uint32_t(i);
+        for (int j = 0; j < D; ++j) std::memcpy(&rec.w[j], &pts[int64_t(i) * D + j], 4);
+        rec.w[D] = uint32_t(i);
         // ancestors by 1-based id: a = (pos+1) >> m, level floor(log2 a)
         int64_t a = (pos + 1) >> 1;
         for (int m = 0; m < rec_ancestors(D); ++m, a >>= 1) {
             if (a < 1) break;
             const int lvl = 63 - __builtin_clzll((unsigned long long)a);
-            std::memcpy(&r[pos].w[D + 1 + m], &pts[int64_t(order[a - 1]) * D + (lvl % D)], 4);
+            std::memcpy(&rec.w[D + 1 + m], &pts[int64_t(order[a - 1]) * D + (lvl % D)], 4);
         }
     }
 }

@@ -57,7 +57,7 @@ struct kd_tree_s {
     int device = 0;
     float lo[4] = {0, 0, 0, 0};
     float hi[4] = {0, 0, 0, 0};
-    void* d_nodes = nullptr;       // TreeRec<dim>[N], level order
+    void* d_nodes = nullptr;       // TreeRec<dim>[N + 2]: record of node id i at index i
     std::vector<int32_t> order;    // host copy: order[pos] = caller index
     std::mutex tune_mu;
     std::vector<kd::TuneEntry> tuned;
@@ -117,7 +117,7 @@ int k_template(int k);
 // One job of a batched call, as the device sees it.  Jobs of one (dim, K)
 // class are laid out back to back in a class slot space.
 struct BatchJob {
-    const void* nodes;       // TreeRec<D>[N], level order
+    const void* nodes;       // TreeRec<D>[N + 2], record of node id i at index i
     const float* queries;    // caller [Q][D]
     int32_t* out_idx;        // caller [Q][k]
     float* out_d2;           // caller [Q][k] or NULL
@@ -147,6 +147,9 @@ kd_status run_batch_class(const BatchJob* d_jobs, int njobs, int dim, int K, uin
                           void* recs, uint32_t* counters, const QueryPlan& plan, int device, hipStream_t st);
 size_t batch_rec_bytes();
 // Morton reorder of query slots (kd_sort.hip)
+size_t bucket_scratch_bytes(int64_t Q, int B);
+kd_status bucket_sort_gather(kd_tree t, const float* queries, int64_t Q, int B, void* ws, void* sq,
+                             uint32_t* extra, uint32_t nextra, hipStream_t st);
 size_t sort_scratch_bytes(int64_t Q);
 kd_status morton_sort(kd_tree t, const float* queries, int64_t Q, int sort_bits, void* ws, hipStream_t st,
                       const uint32_t** perm_out);

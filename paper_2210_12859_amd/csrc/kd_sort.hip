@@ -209,7 +209,110 @@ __global__ void batch_morton_codes(const BatchJob* __restrict__ jobs, int njobs,
     vals[i] = i;
 }
 
+// ---- counting sort on the top B <= 20 Morton bits, fused with the gather ----
+// The order of queries inside one bucket does not matter (a query's result
+// never depends on which lane serves it or when), so buckets are filled with
+// atomics: zero -> count -> exclusive scan -> scatter the gathered record.
+
+__global__ void bucket_zero(uint32_t* __restrict__ cnt, uint32_t nb, uint32_t* __restrict__ extra, uint32_t nextra) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) cnt[i] = 0;
+    if (i < nextra) extra[i] = 0;
+}
+
+__global__ void bucket_count(MortonArgs a, int B, uint32_t* __restrict__ cnt, uint32_t* __restrict__ bucket) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.Q) return;
+    const int bits = a.D == 2 ? 16 : (a.D == 3 ? 10 : 8);
+    const float maxc = float((1u << bits) - 1);
+    uint32_t code = 0;
+    for (int j = 0; j < a.D; ++j) {
+        float u = (a.queries[size_t(i) * a.D + j] - a.lo[j]) * a.scale[j];
+        u = u != u ? 0.0f : fminf(fmaxf(u, 0.0f), maxc);
+        code |= spread_bits(uint32_t(u), a.D) << (a.D - 1 - j);
+    }
+    if (a.D == 3) code <<= 2;
+    const uint32_t b = code >> (32 - B);
+    bucket[i] = b;
+    atomicAdd(&cnt[b], 1u);
+}
+
+// exclusive scan of cnt[0..nb) in place (one workgroup of 1024 threads)
+__global__ __launch_bounds__(1024) void bucket_scan(uint32_t* __restrict__ cnt, uint32_t nb) {
+    __shared__ uint32_t part[1024];
+    const uint32_t t = threadIdx.x;
+    const uint32_t per = (nb + 1023) / 1024;
+    const uint32_t b = t * per;
+    const uint32_t e = b + per < nb ? b + per : nb;
+    uint32_t sum = 0;
+    for (uint32_t i = b; i < e; ++i) sum += cnt[i];
+    part[t] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = t ? part[t - 1] : 0u;
+    for (uint32_t i = b; i < e; ++i) {
+        const uint32_t v = cnt[i];
+        cnt[i] = run;
+        run += v;
+    }
+}
+
+template <int D>
+__global__ void bucket_scatter(const float* __restrict__ queries, uint32_t Q, const uint32_t* __restrict__ bucket,
+                               uint32_t* __restrict__ cursor, NodeRec<D>* __restrict__ sq) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Q) return;
+    const uint32_t pos = atomicAdd(&cursor[bucket[i]], 1u);
+    NodeRec<D> r;
+#pragma unroll
+    for (int j = 0; j < D; ++j) r.c[j] = queries[size_t(i) * D + j];
+    r.idx = int32_t(i);
+    sq[pos] = r;
+}
+
 }  // namespace
+
+size_t bucket_scratch_bytes(int64_t Q, int B) {
+    return (size_t(1) << B) * sizeof(uint32_t) + size_t(Q) * sizeof(uint32_t) + 256;
+}
+
+// Counting sort of the queries on the top B Morton bits (1 <= B <= 20); the
+// scatter writes the gathered traversal-order records into sq.  Also zeroes
+// `extra` (nextra words) on the way.
+kd_status bucket_sort_gather(kd_tree t, const float* queries, int64_t Q, int B, void* ws, void* sq,
+                             uint32_t* extra, uint32_t nextra, hipStream_t st) {
+    const uint32_t n = uint32_t(Q);
+    const uint32_t nb = 1u << B;
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(ws);
+    uint32_t* bucket = cnt + nb;
+    MortonArgs a;
+    a.queries = queries;
+    a.Q = n;
+    a.D = t->dim;
+    const int bits = t->dim == 2 ? 16 : (t->dim == 3 ? 10 : 8);
+    for (int j = 0; j < 4; ++j) {
+        const float ext = t->hi[j] - t->lo[j];
+        a.lo[j] = t->lo[j];
+        a.scale[j] = (j < t->dim && ext > 0.0f) ? float(1u << bits) / ext : 0.0f;
+    }
+    const uint32_t nz = nb > nextra ? nb : nextra;
+    hipLaunchKernelGGL(bucket_zero, dim3((nz + 255) / 256), dim3(256), 0, st, cnt, nb, extra, nextra);
+    hipLaunchKernelGGL(bucket_count, dim3((n + 255) / 256), dim3(256), 0, st, a, B, cnt, bucket);
+    hipLaunchKernelGGL(bucket_scan, dim3(1), dim3(1024), 0, st, cnt, nb);
+    const dim3 g((n + 255) / 256), b(256);
+    switch (t->dim) {
+        case 2: hipLaunchKernelGGL(bucket_scatter<2>, g, b, 0, st, queries, n, bucket, cnt, (NodeRec<2>*)sq); break;
+        case 3: hipLaunchKernelGGL(bucket_scatter<3>, g, b, 0, st, queries, n, bucket, cnt, (NodeRec<3>*)sq); break;
+        default: hipLaunchKernelGGL(bucket_scatter<4>, g, b, 0, st, queries, n, bucket, cnt, (NodeRec<4>*)sq); break;
+    }
+    KD_HIP(hipGetLastError());
+    return KD_OK;
+}
 
 size_t batch_sort_scratch_bytes(int64_t n) {
     const size_t ntiles = size_t((n + SORT_TILE - 1) / SORT_TILE);

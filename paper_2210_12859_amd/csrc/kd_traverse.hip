@@ -46,6 +46,12 @@
 
 #include "kd_internal.h"
 
+// Compile-time variants (results identical; speed differs): prefetch both
+// children of the current node in the same trip.
+#ifndef KD_CHILD_PREFETCH
+#define KD_CHILD_PREFETCH 0
+#endif
+
 namespace kd {
 
 namespace {
@@ -53,7 +59,7 @@ namespace {
 constexpr uint32_t SENT_IDX = 0x7fffffffu;
 
 struct TravArgs {
-    const void* nodes;       // TreeRec<D>[N], level order
+    const void* nodes;       // TreeRec<D>[N + 2], record of node id i at index i
     int32_t N;
     const void* sq;          // NodeRec<D>[Q]: queries in traversal order, .idx = caller row
     uint32_t Q;              // query slots
@@ -117,6 +123,52 @@ __device__ __forceinline__ void load_tree(const TreeRec<D>* p, float (&c)[D], in
     if (RW == 8) {
         const uint4 hi = reinterpret_cast<const uint4*>(p)[1];
         w[4] = hi.x; w[5] = hi.y; w[6] = hi.z; w[7] = hi.w;
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = __uint_as_float(w[j]);
+    idx = int32_t(w[D]);
+    anc[0] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < rec_ancestors(D); ++j) anc[j] = __uint_as_float(w[D + 1 + j]);
+}
+
+// Raw record words (RW/4 vectors) and their decoding.
+template <int D>
+struct RawRec {
+    uint4 v[rec_words(D) / 4];
+};
+
+template <int D>
+__device__ __forceinline__ RawRec<D> load_raw(const TreeRec<D>* p) {
+    RawRec<D> r;
+#pragma unroll
+    for (int i = 0; i < rec_words(D) / 4; ++i) r.v[i] = reinterpret_cast<const uint4*>(p)[i];
+    return r;
+}
+
+template <int D>
+__device__ __forceinline__ RawRec<D> select_raw(bool second, const RawRec<D>& a, const RawRec<D>& b) {
+    RawRec<D> r;
+#pragma unroll
+    for (int i = 0; i < rec_words(D) / 4; ++i) {
+        r.v[i].x = second ? b.v[i].x : a.v[i].x;
+        r.v[i].y = second ? b.v[i].y : a.v[i].y;
+        r.v[i].z = second ? b.v[i].z : a.v[i].z;
+        r.v[i].w = second ? b.v[i].w : a.v[i].w;
+    }
+    return r;
+}
+
+template <int D>
+__device__ __forceinline__ void decode_raw(const RawRec<D>& r, float (&c)[D], int32_t& idx,
+                                           float (&anc)[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1]) {
+    uint32_t w[8];
+#pragma unroll
+    for (int i = 0; i < rec_words(D) / 4; ++i) {
+        w[4 * i + 0] = r.v[i].x;
+        w[4 * i + 1] = r.v[i].y;
+        w[4 * i + 2] = r.v[i].z;
+        w[4 * i + 3] = r.v[i].w;
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) c[j] = __uint_as_float(w[j]);
@@ -365,7 +417,7 @@ constexpr int max_block(int K) { return K >= 32 ? 256 : 1024; }
 
 template <int D, int K, int F, bool LEARNED>
 __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
-    const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes) - 1;  // 1-based
+    const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);  // indexed by node id
     const NodeRec<D>* __restrict__ sq = reinterpret_cast<const NodeRec<D>*>(a.sq);
 
     const uint32_t lane = __lane_id();
@@ -379,6 +431,8 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
     uint32_t cpos = 0, cn = 0;
 
     Lane<D, K> s;
+    RawRec<D> pf0, pf1;     // prefetched children of node pf_parent
+    int32_t pf_parent = -1;
     bool active = false;
     for (;;) {
         const uint64_t need = __ballot(!active);
@@ -426,7 +480,28 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
             float c[D];
             int32_t idx;
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
-            load_tree<D>(g1 + s.curr, c, idx, anc);
+            if (KD_CHILD_PREFETCH) {
+                // The records of curr's two children are requested in the same
+                // trip as curr's own (they sit in one aligned pair), so a
+                // descent finds its next node already in registers.
+                const int32_t cur = s.curr;
+                const bool have = (cur >> 1) == pf_parent;
+                RawRec<D> own;
+                if (!have) own = load_raw<D>(g1 + cur);
+                RawRec<D> n0, n1;
+                const bool kids = 2 * cur <= a.N;
+                if (kids) {
+                    n0 = load_raw<D>(g1 + 2 * cur);
+                    n1 = load_raw<D>(g1 + 2 * cur + 1);
+                }
+                if (have) own = select_raw<D>(cur & 1, pf0, pf1);
+                decode_raw<D>(own, c, idx, anc);
+                pf0 = n0;
+                pf1 = n1;
+                pf_parent = kids ? cur : -1;
+            } else {
+                load_tree<D>(g1 + s.curr, c, idx, anc);
+            }
             const int32_t next = lane_step<D, K, F>(s, c, idx, anc, a.N);
             if (next == 0) {
                 if (LEARNED && lane_needs_restart<D, K>(s, a.R2)) {
@@ -583,7 +658,7 @@ struct BatchArgs {
 
 template <int D, int K>
 struct JobLane {
-    const TreeRec<D>* g1;  // 1-based record pointer of the lane's tree
+    const TreeRec<D>* g1;  // the lane's tree, indexed by node id
     int32_t N;
     int32_t k;
     int32_t* oi;
@@ -595,7 +670,7 @@ template <int D, int K>
 __device__ __forceinline__ void batch_start(Lane<D, K>& s, JobLane<D, K>& j, const BatchJob* jobs,
                                             const BRec& r) {
     const BatchJob& J = jobs[r.job];
-    j.g1 = reinterpret_cast<const TreeRec<D>*>(J.nodes) - 1;
+    j.g1 = reinterpret_cast<const TreeRec<D>*>(J.nodes);
     j.N = J.N;
     j.k = J.k;
     j.oi = J.out_idx;
@@ -824,7 +899,11 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     // scratch: [range cursors | restart count] queries  sort  worst0
     const size_t head = 72 * 1024;
     const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
-    const size_t sort_bytes = plan.sort_bits > 0 ? sort_scratch_bytes(Q) : 0;
+    // sort_bits <= 16: one counting sort whose scatter is the gather; more
+    // bits: stable radix sort, then gather
+    const bool bucket = plan.sort_bits > 0 && plan.sort_bits <= 16;
+    const size_t sort_bytes = bucket ? bucket_scratch_bytes(Q, plan.sort_bits)
+                                     : (plan.sort_bits > 0 ? sort_scratch_bytes(Q) : 0);
     const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
     const size_t learn_bytes = learned ? q4 : 0;
     kd_status s = scratch(stream, head + sq_bytes + sort_bytes + learn_bytes, &ws);
@@ -835,16 +914,26 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     void* sq = base + head;
     void* sort_ws = base + head + sq_bytes;
     float* worst0 = learned ? reinterpret_cast<float*>(base + head + sq_bytes + sort_bytes) : nullptr;
+    const uint32_t n_counters = 16 * 1024 + 1;  // range cursors and the restart count
 
     // query reorder: Morton sort, then gather into traversal order
-    const uint32_t* perm = nullptr;
     hipEvent_t evs;
     s = timing_begin(st, &evs);
     if (s != KD_OK) return s;
-    s = morton_sort(t, queries, Q, plan.sort_bits, sort_ws, st, &perm);
-    if (s != KD_OK) return s;
-    hipError_t e = launch_gather(t->dim, queries, perm, uint32_t(Q), sq, st);
-    if (e != hipSuccess) return hip_error(e, "gather_queries launch");
+    hipError_t e = hipSuccess;
+    if (bucket) {
+        s = bucket_sort_gather(t, queries, Q, plan.sort_bits, sort_ws, sq, counter1, n_counters, st);
+        if (s != KD_OK) return s;
+    } else {
+        const uint32_t* perm = nullptr;
+        s = morton_sort(t, queries, Q, plan.sort_bits, sort_ws, st, &perm);
+        if (s != KD_OK) return s;
+        e = launch_gather(t->dim, queries, perm, uint32_t(Q), sq, st);
+        if (e != hipSuccess) return hip_error(e, "gather_queries launch");
+        hipLaunchKernelGGL(zero_u32, dim3(unsigned((n_counters + 255) / 256)), dim3(256), 0, st, counter1,
+                           int(n_counters));
+        KD_HIP(hipGetLastError());
+    }
     s = timing_end(st, evs, "sort");
     if (s != KD_OK) return s;
 
@@ -895,10 +984,6 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     if (grid > need) grid = need;
     if (grid > 8 && grid % 8) grid -= grid % 8;
     if (grid < 1) grid = 1;
-    // zero the cursors and the restart count
-    hipLaunchKernelGGL(zero_u32, dim3(unsigned((16 * 1024 + 1 + 255) / 256)), dim3(256), 0, st, counter1,
-                       16 * 1024 + 1);
-    KD_HIP(hipGetLastError());
     hipEvent_t ev0;
     s = timing_begin(st, &ev0);
     if (s != KD_OK) return s;
