@@ -44,6 +44,8 @@
 //     a fixed, fully unrolled network behind a wave-uniform skip.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kd_internal.h"
 
 // Compile-time variants (results identical; speed differs): prefetch both
@@ -99,17 +101,23 @@ __device__ __forceinline__ int dim_up(int d) { return d == 0 ? D - 1 : d - 1; }
 template <int D>
 __device__ __forceinline__ int dim_down(int d) { return d == D - 1 ? 0 : d + 1; }
 
-// v[(dim - i) mod D]; the compares against constants are shared across calls.
-// (I is a constant after unrolling, so the compares are against constants.)
-template <int D>
-__device__ __forceinline__ float sel_rot(const float (&v)[D], int dim, int I) {
-    float r = v[(D - I % D) % D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        const int want = (j + I) % D;  // dim value for which v[j] is picked
-        if (want != 0) r = (dim == want) ? v[j] : r;
-    }
+// v[(dim - I) mod D] as a chain of selects on compile-time constants (a
+// dynamically indexed local array would be placed in LDS by the compiler).
+template <int D, int I>
+__device__ __forceinline__ float sel_rot(float v0, float v1, float v2, float v3, int dim) {
+    // dim == (j + I) mod D picks v_j
+    constexpr int j0 = (D - I % D) % D;  // the pick for dim == 0
+    float r = j0 == 0 ? v0 : (j0 == 1 ? v1 : (j0 == 2 ? v2 : v3));
+    if ((1 + I) % D != 0) r = dim == (1 + I) % D ? v1 : r;
+    if (D > 2 && (2 + I) % D != 0) r = dim == (2 + I) % D ? v2 : r;
+    if (D > 3 && (3 + I) % D != 0) r = dim == (3 + I) % D ? v3 : r;
+    if ((0 + I) % D != 0) r = dim == (0 + I) % D ? v0 : r;
     return r;
+}
+
+template <int D, int I>
+__device__ __forceinline__ float sel_rot(const float (&v)[D], int dim) {
+    return sel_rot<D, I>(v[0], v[1], D > 2 ? v[D > 2 ? 2 : 0] : 0.0f, D > 3 ? v[D > 3 ? 3 : 0] : 0.0f, dim);
 }
 
 // Whole-record loads: one or two dwordx4 from one aligned record.
@@ -304,7 +312,7 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     float dx[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) dx[j] = s.q[j] - c[j];
-    const float sd = sel_rot<D>(dx, dim, 0);
+    const float sd = sel_rot<D, 0>(dx, dim);
     const bool from_parent = s.prev < curr;
     // processNode on the first visit: exact binary32 squared distance, left
     // to right (computed branch-free; only the insertion is conditional).
@@ -333,12 +341,12 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     // dimension dim-1-i): the lane came from `child`; if that is the close
     // child and the far subtree is in range, step to the far child, else
     // keep returning.
-#pragma unroll
-    for (int i = 0; i < F; ++i) {
+    auto fused = [&](auto ic) {
+        constexpr int i = decltype(ic)::value;
         const bool live = up & (anc_id != 0);
         if (__any(live)) {
             if (live) {
-                const float sda = sel_rot<D>(s.q, dim, i + 1) - anc[i];
+                const float sda = sel_rot<D, i + 1>(s.q, dim) - anc[i];
                 const bool child_is_close = (child & 1) == (sda > 0.0f ? 1 : 0);
                 const int32_t fa = child ^ 1;
                 const bool take_far = child_is_close & (sda * sda <= worst) & (fa <= N);
@@ -352,7 +360,10 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
                 }
             }
         }
-    }
+    };
+    if constexpr (F >= 1) fused(std::integral_constant<int, 0>{});
+    if constexpr (F >= 2) fused(std::integral_constant<int, 1>{});
+    if constexpr (F >= 3) fused(std::integral_constant<int, 2>{});
     if (up) {
         next = anc_id;  // 0 once the root has returned: finished
         nprev = child;
