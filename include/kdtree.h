@@ -67,7 +67,8 @@ typedef struct {
                         also accepted; 0 = default (256) */
     int lds_levels;  /* reserved, ignored (0 or -1) */
     int sort_bits;   /* Morton bits the queries are sorted on before traversal:
-                        0 (keep the caller's order), 8, 16, 24 or 32; -1 = default (16) */
+                        0 keeps the caller's order; 1..32 is rounded up to a
+                        whole byte (8, 16, 24, 32); -1 = default (16) */
     int waves_per_cu;/* persistent grid size in waves per compute unit (capped by
                         occupancy); 0 = default (24) */
 } kd_opts;

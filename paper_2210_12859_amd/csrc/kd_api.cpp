@@ -217,9 +217,8 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     if (use.block != 64 && use.block != 128 && use.block != 256 && use.block != 512 && use.block != 1024)
         return set_error(KD_EINVAL, "opts.block must be 64, 128, 256, 512 or 1024");
     if (use.lds_levels > 13) return set_error(KD_EINVAL, "opts.lds_levels must be <= 13");
-    if (use.sort_bits != 0 && use.sort_bits != 8 && use.sort_bits != 16 && use.sort_bits != 24 &&
-        use.sort_bits != 32)
-        return set_error(KD_EINVAL, "opts.sort_bits must be 0, 8, 16, 24 or 32");
+    if (use.sort_bits > 32) return set_error(KD_EINVAL, "opts.sort_bits must be in 0..32 or -1");
+    use.sort_bits = ((use.sort_bits + 7) / 8) * 8;  // the radix sort takes whole bytes
     if (use.waves_per_cu < 1 || use.waves_per_cu > 32) return set_error(KD_EINVAL, "opts.waves_per_cu must be in 1..32");
     p.block = use.block;
     p.lds_levels = use.lds_levels;

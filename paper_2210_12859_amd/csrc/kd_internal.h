@@ -147,12 +147,12 @@ kd_status run_batch_class(const BatchJob* d_jobs, int njobs, int dim, int K, uin
                           void* recs, uint32_t* counters, const QueryPlan& plan, int device, hipStream_t st);
 size_t batch_rec_bytes();
 // Morton reorder of query slots (kd_sort.hip)
-size_t bucket_scratch_bytes(int64_t Q, int B);
-kd_status bucket_sort_gather(kd_tree t, const float* queries, int64_t Q, int B, void* ws, void* sq,
-                             uint32_t* extra, uint32_t nextra, hipStream_t st);
-size_t sort_scratch_bytes(int64_t Q);
-kd_status morton_sort(kd_tree t, const float* queries, int64_t Q, int sort_bits, void* ws, hipStream_t st,
-                      const uint32_t** perm_out);
+size_t sort_scratch_bytes(int64_t Q, int dim);
+// Writes the queries as traversal records (NodeRec<dim>[Q]) into sq, in
+// Morton order on the top sort_bits bits (0: caller order), and clears
+// zero[0..nzero) on the way.  ws holds sort_scratch_bytes(Q, dim) when sort_bits > 0.
+kd_status reorder_queries(kd_tree t, const float* queries, int64_t Q, int sort_bits, void* ws, void* sq,
+                          uint32_t* zero, uint32_t nzero, hipStream_t st);
 kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan, int32_t* out_idx,
                   float* out_d2, uint32_t* visited, kd_stream stream, const LearnedSpec* learned = nullptr,
                   uint32_t* fallbacks_out = nullptr);

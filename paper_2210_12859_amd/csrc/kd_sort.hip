@@ -1,17 +1,26 @@
-// kd_sort.hip -- Morton codes and a stable LSD radix sort of (code, index)
-// pairs, used to reorder query batches along a Z-order curve so that queries
-// that run together (in one wave, one CU, one XCD) traverse the same parts of
-// the tree.  The reorder changes only the order in which queries are served,
-// never any result.
+// kd_sort.hip -- reorders query batches along a Z-order (Morton) curve so
+// that queries served together (one wave, one CU, one XCD) traverse the same
+// parts of the tree.  The reorder changes only which lane serves a query and
+// when, never a result.
 //
-// One sort pass over an 8-bit digit is three kernels:
-//   radix_hist    per-tile digit counts            -> hist[digit][tile]
-//   radix_scan    per-digit exclusive scan over tiles, in place, + digit totals
+// Stable LSD radix sort of (Morton code, caller row) on the top sort_bits
+// bits, 8 bits per pass; one pass is three kernels:
+//   radix_hist    per-tile digit counts                  -> hist[digit][tile]
+//   radix_scan    per digit, exclusive scan over tiles (in place) + totals
 //   radix_scatter stable rank of every key inside its tile (wave ballots over
-//                 the digit bits + LDS prefix over waves and rounds), then
-//                 out[digit base + tile offset + rank]
-// A tile is 256 threads x 16 rounds = 4096 keys; round r covers keys
-// [r*256, (r+1)*256) of the tile, so tile order is preserved.
+//                 the digit bits + LDS counts over waves and rounds), written
+//                 at digit base + tile offset + rank
+// A tile is 4096 keys, 1024 threads x 4 rounds; round r covers keys
+// [r*1024, (r+1)*1024) of the tile.  The scatter first reorders its tile by
+// digit in LDS and then writes each digit's run of keys to consecutive
+// addresses, so the stores coalesce (about 16 keys per digit and tile for
+// random digits) instead of touching a different cache line per key.
+//
+// For a single tree the keys travel with the 16/32-byte traversal records
+// (coordinates + caller row) instead of a row index, so no pass gathers at
+// random: the first pass reads the queries and computes the codes itself, the
+// last pass writes only the records, and the first kernel also clears the
+// traversal's work counters.  A 16-bit sort is 6 kernels.
 #include <hip/hip_runtime.h>
 
 #include "kd_internal.h"
@@ -20,9 +29,13 @@ namespace kd {
 
 namespace {
 
-constexpr int SORT_THREADS = 256;
-constexpr int SORT_ROUNDS = 16;
-constexpr int SORT_TILE = SORT_THREADS * SORT_ROUNDS;
+constexpr int SCAN_THREADS = 256;    // radix_scan: one workgroup per digit
+constexpr int TILE_THREADS = 1024;   // radix_hist / radix_scatter
+constexpr int TILE_WAVES = TILE_THREADS / 64;
+constexpr int TILE_ROUNDS = 4;
+constexpr int SORT_TILE = TILE_THREADS * TILE_ROUNDS;  // 4096 keys
+
+uint32_t sort_tiles(uint32_t n) { return (n + SORT_TILE - 1) / SORT_TILE; }
 
 __device__ __forceinline__ uint32_t spread_bits(uint32_t v, int D) {
     // insert D-1 zero bits between the low bits of v
@@ -50,50 +63,89 @@ __device__ __forceinline__ uint32_t spread_bits(uint32_t v, int D) {
 struct MortonArgs {
     const float* queries;
     uint32_t Q;
-    int D;
     float lo[4];
     float scale[4];  // (2^bits) / extent, 0 for a flat axis
 };
 
-// 32-bit code, most significant spatial bit in bit 31 (D=3 uses bits 2..31).
-__global__ void morton_codes(MortonArgs a, uint32_t* __restrict__ codes, uint32_t* __restrict__ vals) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.Q) return;
-    const int bits = a.D == 2 ? 16 : (a.D == 3 ? 10 : 8);
+// 32-bit code of D coordinates, most significant spatial bit in bit 31
+// (D = 3 uses bits 2..31).  NaN maps to cell 0, outside the box clamps.
+template <int D>
+__device__ __forceinline__ uint32_t morton_code(const float* c, const float* lo, const float* scale) {
+    constexpr int bits = D == 2 ? 16 : (D == 3 ? 10 : 8);
     const float maxc = float((1u << bits) - 1);
     uint32_t code = 0;
-    for (int j = 0; j < a.D; ++j) {
-        float u = (a.queries[size_t(i) * a.D + j] - a.lo[j]) * a.scale[j];
-        u = u != u ? 0.0f : fminf(fmaxf(u, 0.0f), maxc);  // NaN -> 0, clamp
-        code |= spread_bits(uint32_t(u), a.D) << (a.D - 1 - j);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        float u = (c[j] - lo[j]) * scale[j];
+        u = u != u ? 0.0f : fminf(fmaxf(u, 0.0f), maxc);
+        code |= spread_bits(uint32_t(u), D) << (D - 1 - j);
     }
-    if (a.D == 3) code <<= 2;
-    codes[i] = code;
-    vals[i] = i;
+    if (D == 3) code <<= 2;
+    return code;
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void radix_hist(const uint32_t* __restrict__ keys, uint32_t n,
-                                                           int shift, uint32_t* __restrict__ hist,
-                                                           uint32_t ntiles) {
+// One radix pass.  D = 0: keys and rows come from kin/vin and go to
+// kout/vout.  D > 0: keys travel with NodeRec<D> records (coordinates +
+// caller row) kin/rin -> kout/rout; FROM_Q computes the keys and records from
+// the queries (row = slot), TO_REC writes only the records, to `rec`.
+struct SortPass {
+    const uint32_t* kin;
+    const uint32_t* vin;
+    const void* rin;
+    uint32_t* kout;
+    uint32_t* vout;
+    void* rout;
+    void* rec;
+    MortonArgs m;
+    uint32_t n;
+    int shift;
+    uint32_t ntiles;
+    uint32_t* hist;
+    uint32_t* totals;
+    uint32_t* zero;   // cleared by radix_hist (nzero words), may be NULL
+    uint32_t nzero;
+};
+
+template <int D>
+__device__ __forceinline__ void load_query(const MortonArgs& m, uint32_t row, float* c) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = m.queries[size_t(row) * D + j];
+}
+
+template <int D, bool FROM_Q>
+__global__ __launch_bounds__(TILE_THREADS) void radix_hist(SortPass p) {
     __shared__ uint32_t cnt[256];
-    cnt[threadIdx.x] = 0;
+    const uint32_t t = threadIdx.x;
+    if (t < 256) cnt[t] = 0;
+    for (uint32_t i = blockIdx.x * TILE_THREADS + t; i < p.nzero; i += gridDim.x * TILE_THREADS) p.zero[i] = 0;
     __syncthreads();
-    const uint32_t base = blockIdx.x * SORT_TILE;
-    for (int r = 0; r < SORT_ROUNDS; ++r) {
-        const uint32_t i = base + r * SORT_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 0xffu], 1u);
+    const uint32_t base = blockIdx.x * uint32_t(SORT_TILE);
+#pragma unroll
+    for (int r = 0; r < TILE_ROUNDS; ++r) {
+        const uint32_t i = base + r * TILE_THREADS + t;
+        if (i < p.n) {
+            uint32_t key;
+            if constexpr (FROM_Q) {
+                float c[D > 0 ? D : 1];
+                load_query<D>(p.m, i, c);
+                key = morton_code<D>(c, p.m.lo, p.m.scale);
+            } else {
+                key = p.kin[i];
+            }
+            atomicAdd(&cnt[(key >> p.shift) & 0xffu], 1u);
+        }
     }
     __syncthreads();
-    hist[size_t(threadIdx.x) * ntiles + blockIdx.x] = cnt[threadIdx.x];
+    if (t < 256) p.hist[size_t(t) * p.ntiles + blockIdx.x] = cnt[t];
 }
 
 // One block per digit: exclusive scan of hist[digit][0..ntiles) in place;
 // totals[digit] = sum.
-__global__ __launch_bounds__(SORT_THREADS) void radix_scan(uint32_t* __restrict__ hist, uint32_t ntiles,
+__global__ __launch_bounds__(SCAN_THREADS) void radix_scan(uint32_t* __restrict__ hist, uint32_t ntiles,
                                                            uint32_t* __restrict__ totals) {
-    __shared__ uint32_t part[SORT_THREADS];
+    __shared__ uint32_t part[SCAN_THREADS];
     uint32_t* row = hist + size_t(blockIdx.x) * ntiles;
-    const uint32_t per = (ntiles + SORT_THREADS - 1) / SORT_THREADS;
+    const uint32_t per = (ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
     const uint32_t b = threadIdx.x * per;
     const uint32_t e = b + per < ntiles ? b + per : ntiles;
     uint32_t s = 0;
@@ -101,7 +153,7 @@ __global__ __launch_bounds__(SORT_THREADS) void radix_scan(uint32_t* __restrict_
     part[threadIdx.x] = s;
     __syncthreads();
     // inclusive scan of part (Hillis-Steele)
-    for (int off = 1; off < SORT_THREADS; off <<= 1) {
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
         uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
         __syncthreads();
         part[threadIdx.x] += v;
@@ -113,43 +165,78 @@ __global__ __launch_bounds__(SORT_THREADS) void radix_scan(uint32_t* __restrict_
         row[i] = run;
         run += v;
     }
-    if (threadIdx.x == SORT_THREADS - 1) totals[blockIdx.x] = part[SORT_THREADS - 1];
+    if (threadIdx.x == SCAN_THREADS - 1) totals[blockIdx.x] = part[SCAN_THREADS - 1];
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void radix_scatter(const uint32_t* __restrict__ kin,
-                                                              const uint32_t* __restrict__ vin, uint32_t n,
-                                                              int shift, const uint32_t* __restrict__ hist,
-                                                              uint32_t ntiles, const uint32_t* __restrict__ totals,
-                                                              uint32_t* __restrict__ kout,
-                                                              uint32_t* __restrict__ vout) {
-    __shared__ uint32_t base_d[256];      // digit base + this tile's offset, advanced per round
-    __shared__ uint32_t wcnt[4][256];     // per-wave digit counts of the current round
-    __shared__ uint32_t tmp[256];
-    const int t = threadIdx.x;
-    const int w = t >> 6;
-    // exclusive scan of totals -> digit base
-    tmp[t] = totals[t];
+// Inclusive scan of v over the first 256 threads; every thread of the block
+// takes part in the barriers.
+__device__ __forceinline__ uint32_t scan256(uint32_t* buf, uint32_t v) {
+    const uint32_t t = threadIdx.x;
+    if (t < 256) buf[t] = v;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        uint32_t v = t >= off ? tmp[t - off] : 0u;
+    for (uint32_t off = 1; off < 256; off <<= 1) {
+        uint32_t x = 0;
+        if (t < 256 && t >= off) x = buf[t - off];
         __syncthreads();
-        tmp[t] += v;
+        if (t < 256) buf[t] += x;
         __syncthreads();
     }
-    base_d[t] = (t ? tmp[t - 1] : 0u) + hist[size_t(t) * ntiles + blockIdx.x];
-    for (int ww = 0; ww < 4; ++ww) wcnt[ww][t] = 0;
+    return t < 256 ? buf[t] : 0u;
+}
+
+template <int D, bool FROM_Q, bool TO_REC>
+__global__ __launch_bounds__(TILE_THREADS) void radix_scatter(SortPass p) {
+    static_assert(D > 0 || (!FROM_Q && !TO_REC), "queries need a dimension");
+    __shared__ uint32_t gbase[256];              // output position of the tile's first key of digit d
+    __shared__ uint32_t lstart[256];             // tile position of the first key of digit d
+    __shared__ uint32_t lnext[256];              // next free tile position of digit d
+    __shared__ uint32_t sbuf[256];
+    __shared__ uint32_t wcnt[TILE_WAVES][256];   // digit counts per wave -> prefix over waves
+    __shared__ uint32_t skey[SORT_TILE];
+    __shared__ uint32_t sval[SORT_TILE];         // tile index of the key
+    const uint32_t t = threadIdx.x;
+    const uint32_t w = t >> 6;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t tile0 = tile * uint32_t(SORT_TILE);
+    const uint32_t tile_n = p.n - tile0 < uint32_t(SORT_TILE) ? p.n - tile0 : uint32_t(SORT_TILE);
+
+    // digit bases: global (all smaller digits + this digit in earlier tiles)
+    // and local (smaller digits in this tile)
+    uint32_t tot = 0, before = 0, mine = 0;
+    if (t < 256) {
+        tot = p.totals[t];
+        before = p.hist[size_t(t) * p.ntiles + tile];
+        const uint32_t after = tile + 1 < p.ntiles ? p.hist[size_t(t) * p.ntiles + tile + 1] : tot;
+        mine = after - before;
+    }
+    const uint32_t incl_tot = scan256(sbuf, tot);
+    if (t < 256) gbase[t] = incl_tot - tot + before;
+    __syncthreads();
+    const uint32_t incl_mine = scan256(sbuf, mine);
+    if (t < 256) {
+        lstart[t] = incl_mine - mine;
+        lnext[t] = incl_mine - mine;
+    }
+    for (uint32_t j = t; j < uint32_t(TILE_WAVES * 256); j += TILE_THREADS) (&wcnt[0][0])[j] = 0;
     __syncthreads();
 
-    const uint32_t tile0 = blockIdx.x * SORT_TILE;
+    // rank the tile's keys stably by digit; LDS gets (key, tile index)
     const uint64_t lt_mask = (uint64_t(1) << (t & 63)) - 1;
-    for (int r = 0; r < SORT_ROUNDS; ++r) {
-        const uint32_t i = tile0 + r * SORT_THREADS + t;
-        const bool valid = i < n;
-        uint32_t key = 0, val = 0, d = 0;
+#pragma unroll
+    for (int r = 0; r < TILE_ROUNDS; ++r) {
+        const uint32_t li = r * TILE_THREADS + t;
+        const bool valid = li < tile_n;
+        uint32_t key = 0, d = 0;
         if (valid) {
-            key = kin[i];
-            val = vin[i];
-            d = (key >> shift) & 0xffu;
+            const uint32_t i = tile0 + li;
+            if constexpr (FROM_Q) {
+                float c[D > 0 ? D : 1];
+                load_query<D>(p.m, i, c);
+                key = morton_code<D>(c, p.m.lo, p.m.scale);
+            } else {
+                key = p.kin[i];
+            }
+            d = (key >> p.shift) & 0xffu;
         }
         // lanes of this wave holding the same digit
         uint64_t peers = __ballot(valid);
@@ -161,20 +248,70 @@ __global__ __launch_bounds__(SORT_THREADS) void radix_scatter(const uint32_t* __
         const uint32_t rank = __popcll(peers & lt_mask);
         if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
         __syncthreads();
-        if (valid) {
-            uint32_t off = base_d[d] + rank;
-            for (int ww = 0; ww < w; ++ww) off += wcnt[ww][d];
-            kout[off] = key;
-            vout[off] = val;
+        uint32_t round_total = 0;
+        if (t < 256) {
+            for (int ww = 0; ww < TILE_WAVES; ++ww) {
+                const uint32_t c = wcnt[ww][t];
+                wcnt[ww][t] = round_total;
+                round_total += c;
+            }
         }
         __syncthreads();
-        base_d[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
-        wcnt[0][t] = 0;
-        wcnt[1][t] = 0;
-        wcnt[2][t] = 0;
-        wcnt[3][t] = 0;
+        if (valid) {
+            const uint32_t pos = lnext[d] + wcnt[w][d] + rank;
+            if (pos < uint32_t(SORT_TILE)) {  // always, as the counts come from the same keys
+                skey[pos] = key;
+                sval[pos] = li;
+            }
+        }
+        __syncthreads();
+        if (t < 256) {
+            lnext[t] += round_total;
+            for (int ww = 0; ww < TILE_WAVES; ++ww) wcnt[ww][t] = 0;
+        }
         __syncthreads();
     }
+
+    // write the digit runs out: consecutive tile positions of one digit go
+    // to consecutive output positions; the payload is read from this tile's
+    // slice of the input (a window of 4096 entries)
+    for (uint32_t j = t; j < tile_n; j += TILE_THREADS) {
+        const uint32_t key = skey[j];
+        const uint32_t src = tile0 + sval[j];
+        const uint32_t d = (key >> p.shift) & 0xffu;
+        const uint32_t off = gbase[d] + (j - lstart[d]);
+        if (off >= p.n) continue;  // never, as above
+        if constexpr (D == 0) {
+            p.kout[off] = key;
+            p.vout[off] = p.vin[src];
+        } else {
+            NodeRec<D> rec;
+            if constexpr (FROM_Q) {
+                load_query<D>(p.m, src, rec.c);
+                rec.idx = int32_t(src);
+            } else {
+                rec = static_cast<const NodeRec<D>*>(p.rin)[src];
+            }
+            if constexpr (TO_REC) {
+                static_cast<NodeRec<D>*>(p.rec)[off] = rec;
+            } else {
+                p.kout[off] = key;
+                static_cast<NodeRec<D>*>(p.rout)[off] = rec;
+            }
+        }
+    }
+}
+
+// Identity order: copy the queries into records, clear the work counters.
+template <int D>
+__global__ void copy_records(SortPass p) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p.nzero) p.zero[i] = 0;
+    if (i >= p.n) return;
+    NodeRec<D> rec;
+    load_query<D>(p.m, i, rec.c);
+    rec.idx = int32_t(i);
+    static_cast<NodeRec<D>*>(p.rec)[i] = rec;
 }
 
 // Job of class slot i (jobs sorted by slot_base).
@@ -196,126 +333,42 @@ __global__ void batch_morton_codes(const BatchJob* __restrict__ jobs, int njobs,
     const int j = find_job(jobs, njobs, i);
     const BatchJob& J = jobs[j];
     const uint32_t row = i - J.slot_base;
-    const int bits = D == 2 ? 16 : (D == 3 ? 10 : 8);
-    const float maxc = float((1u << bits) - 1);
-    uint32_t code = 0;
-    for (int d = 0; d < D; ++d) {
-        float u = (J.queries[size_t(row) * D + d] - J.lo[d]) * J.scale[d];
-        u = u != u ? 0.0f : fminf(fmaxf(u, 0.0f), maxc);
-        code |= spread_bits(uint32_t(u), D) << (D - 1 - d);
+    float c[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int d = 0; d < D; ++d) c[d] = J.queries[size_t(row) * D + d];
+    uint32_t code;
+    switch (D) {
+        case 2: code = morton_code<2>(c, J.lo, J.scale); break;
+        case 3: code = morton_code<3>(c, J.lo, J.scale); break;
+        default: code = morton_code<4>(c, J.lo, J.scale); break;
     }
-    if (D == 3) code <<= 2;
     codes[i] = jb > 0 ? (uint32_t(j) << (32 - jb)) | (code >> jb) : code;
     vals[i] = i;
 }
 
-// ---- counting sort on the top B <= 20 Morton bits, fused with the gather ----
-// The order of queries inside one bucket does not matter (a query's result
-// never depends on which lane serves it or when), so buckets are filled with
-// atomics: zero -> count -> exclusive scan -> scatter the gathered record.
-
-__global__ void bucket_zero(uint32_t* __restrict__ cnt, uint32_t nb, uint32_t* __restrict__ extra, uint32_t nextra) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nb) cnt[i] = 0;
-    if (i < nextra) extra[i] = 0;
-}
-
-__global__ void bucket_count(MortonArgs a, int B, uint32_t* __restrict__ cnt, uint32_t* __restrict__ bucket) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.Q) return;
-    const int bits = a.D == 2 ? 16 : (a.D == 3 ? 10 : 8);
-    const float maxc = float((1u << bits) - 1);
-    uint32_t code = 0;
-    for (int j = 0; j < a.D; ++j) {
-        float u = (a.queries[size_t(i) * a.D + j] - a.lo[j]) * a.scale[j];
-        u = u != u ? 0.0f : fminf(fmaxf(u, 0.0f), maxc);
-        code |= spread_bits(uint32_t(u), a.D) << (a.D - 1 - j);
-    }
-    if (a.D == 3) code <<= 2;
-    const uint32_t b = code >> (32 - B);
-    bucket[i] = b;
-    atomicAdd(&cnt[b], 1u);
-}
-
-// exclusive scan of cnt[0..nb) in place (one workgroup of 1024 threads)
-__global__ __launch_bounds__(1024) void bucket_scan(uint32_t* __restrict__ cnt, uint32_t nb) {
-    __shared__ uint32_t part[1024];
-    const uint32_t t = threadIdx.x;
-    const uint32_t per = (nb + 1023) / 1024;
-    const uint32_t b = t * per;
-    const uint32_t e = b + per < nb ? b + per : nb;
-    uint32_t sum = 0;
-    for (uint32_t i = b; i < e; ++i) sum += cnt[i];
-    part[t] = sum;
-    __syncthreads();
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = t >= off ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    uint32_t run = t ? part[t - 1] : 0u;
-    for (uint32_t i = b; i < e; ++i) {
-        const uint32_t v = cnt[i];
-        cnt[i] = run;
-        run += v;
-    }
-}
 
 template <int D>
-__global__ void bucket_scatter(const float* __restrict__ queries, uint32_t Q, const uint32_t* __restrict__ bucket,
-                               uint32_t* __restrict__ cursor, NodeRec<D>* __restrict__ sq) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Q) return;
-    const uint32_t pos = atomicAdd(&cursor[bucket[i]], 1u);
-    NodeRec<D> r;
-#pragma unroll
-    for (int j = 0; j < D; ++j) r.c[j] = queries[size_t(i) * D + j];
-    r.idx = int32_t(i);
-    sq[pos] = r;
+hipError_t launch_pass(const SortPass& p, bool first, bool last, hipStream_t st) {
+    const dim3 g(p.ntiles), b(TILE_THREADS), bs(SCAN_THREADS);
+    if constexpr (D == 0) {
+        hipLaunchKernelGGL((radix_hist<0, false>), g, b, 0, st, p);
+        hipLaunchKernelGGL(radix_scan, dim3(256), bs, 0, st, p.hist, p.ntiles, p.totals);
+        hipLaunchKernelGGL((radix_scatter<0, false, false>), g, b, 0, st, p);
+    } else {
+        if (first) hipLaunchKernelGGL((radix_hist<D, true>), g, b, 0, st, p);
+        else hipLaunchKernelGGL((radix_hist<D, false>), g, b, 0, st, p);
+        hipLaunchKernelGGL(radix_scan, dim3(256), bs, 0, st, p.hist, p.ntiles, p.totals);
+        if (first && last) hipLaunchKernelGGL((radix_scatter<D, true, true>), g, b, 0, st, p);
+        else if (first) hipLaunchKernelGGL((radix_scatter<D, true, false>), g, b, 0, st, p);
+        else if (last) hipLaunchKernelGGL((radix_scatter<D, false, true>), g, b, 0, st, p);
+        else hipLaunchKernelGGL((radix_scatter<D, false, false>), g, b, 0, st, p);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
 
-size_t bucket_scratch_bytes(int64_t Q, int B) {
-    return (size_t(1) << B) * sizeof(uint32_t) + size_t(Q) * sizeof(uint32_t) + 256;
-}
-
-// Counting sort of the queries on the top B Morton bits (1 <= B <= 20); the
-// scatter writes the gathered traversal-order records into sq.  Also zeroes
-// `extra` (nextra words) on the way.
-kd_status bucket_sort_gather(kd_tree t, const float* queries, int64_t Q, int B, void* ws, void* sq,
-                             uint32_t* extra, uint32_t nextra, hipStream_t st) {
-    const uint32_t n = uint32_t(Q);
-    const uint32_t nb = 1u << B;
-    uint32_t* cnt = reinterpret_cast<uint32_t*>(ws);
-    uint32_t* bucket = cnt + nb;
-    MortonArgs a;
-    a.queries = queries;
-    a.Q = n;
-    a.D = t->dim;
-    const int bits = t->dim == 2 ? 16 : (t->dim == 3 ? 10 : 8);
-    for (int j = 0; j < 4; ++j) {
-        const float ext = t->hi[j] - t->lo[j];
-        a.lo[j] = t->lo[j];
-        a.scale[j] = (j < t->dim && ext > 0.0f) ? float(1u << bits) / ext : 0.0f;
-    }
-    const uint32_t nz = nb > nextra ? nb : nextra;
-    hipLaunchKernelGGL(bucket_zero, dim3((nz + 255) / 256), dim3(256), 0, st, cnt, nb, extra, nextra);
-    hipLaunchKernelGGL(bucket_count, dim3((n + 255) / 256), dim3(256), 0, st, a, B, cnt, bucket);
-    hipLaunchKernelGGL(bucket_scan, dim3(1), dim3(1024), 0, st, cnt, nb);
-    const dim3 g((n + 255) / 256), b(256);
-    switch (t->dim) {
-        case 2: hipLaunchKernelGGL(bucket_scatter<2>, g, b, 0, st, queries, n, bucket, cnt, (NodeRec<2>*)sq); break;
-        case 3: hipLaunchKernelGGL(bucket_scatter<3>, g, b, 0, st, queries, n, bucket, cnt, (NodeRec<3>*)sq); break;
-        default: hipLaunchKernelGGL(bucket_scatter<4>, g, b, 0, st, queries, n, bucket, cnt, (NodeRec<4>*)sq); break;
-    }
-    KD_HIP(hipGetLastError());
-    return KD_OK;
-}
-
 size_t batch_sort_scratch_bytes(int64_t n) {
-    const size_t ntiles = size_t((n + SORT_TILE - 1) / SORT_TILE);
+    const size_t ntiles = sort_tiles(uint32_t(n));
     return 4 * size_t(n) * sizeof(uint32_t) + (256 * ntiles + 256) * sizeof(uint32_t) + 256;
 }
 
@@ -326,25 +379,27 @@ kd_status batch_sort(const BatchJob* d_jobs, int njobs, int dim, uint32_t n, int
     int jb = 0;
     while ((1 << jb) < njobs) ++jb;
     if (sort_bits <= 0) return KD_OK;  // class slots are already in job order
-    const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+    SortPass p = {};
+    p.n = n;
+    p.ntiles = sort_tiles(n);
     uint32_t* k0 = reinterpret_cast<uint32_t*>(ws);
     uint32_t* v0 = k0 + n;
     uint32_t* k1 = v0 + n;
     uint32_t* v1 = k1 + n;
-    uint32_t* hist = v1 + n;
-    uint32_t* totals = hist + size_t(256) * ntiles;
+    p.hist = v1 + n;
+    p.totals = p.hist + size_t(256) * p.ntiles;
     hipLaunchKernelGGL(batch_morton_codes, dim3((n + 255) / 256), dim3(256), 0, st, d_jobs, njobs, dim, jb, n, k0, v0);
     KD_HIP(hipGetLastError());
     // the job bits must take part in the sort: sort on at least jb top bits
     int bits = sort_bits < jb ? ((jb + 7) / 8) * 8 : sort_bits;
     if (bits > 32) bits = 32;
-    for (int p = 0; p < bits / 8; ++p) {
-        const int shift = 32 - bits + 8 * p;
-        hipLaunchKernelGGL(radix_hist, dim3(ntiles), dim3(SORT_THREADS), 0, st, k0, n, shift, hist, ntiles);
-        hipLaunchKernelGGL(radix_scan, dim3(256), dim3(SORT_THREADS), 0, st, hist, ntiles, totals);
-        hipLaunchKernelGGL(radix_scatter, dim3(ntiles), dim3(SORT_THREADS), 0, st, k0, v0, n, shift, hist, ntiles,
-                           totals, k1, v1);
-        KD_HIP(hipGetLastError());
+    for (int q = 0; q < bits / 8; ++q) {
+        p.shift = 32 - bits + 8 * q;
+        p.kin = k0;
+        p.vin = v0;
+        p.kout = k1;
+        p.vout = v1;
+        KD_HIP(launch_pass<0>(p, false, false, st));
         uint32_t* tk = k0; k0 = k1; k1 = tk;
         uint32_t* tv = v0; v0 = v1; v1 = tv;
     }
@@ -352,51 +407,65 @@ kd_status batch_sort(const BatchJob* d_jobs, int njobs, int dim, uint32_t n, int
     return KD_OK;
 }
 
-size_t sort_scratch_bytes(int64_t Q) {
-    const size_t ntiles = size_t((Q + SORT_TILE - 1) / SORT_TILE);
-    return 4 * size_t(Q) * sizeof(uint32_t) + (256 * ntiles + 256) * sizeof(uint32_t) + 256;
+size_t sort_scratch_bytes(int64_t Q, int dim) {
+    const size_t ntiles = sort_tiles(uint32_t(Q));
+    const size_t rb = dim == 4 ? 32 : 16;
+    return 2 * size_t(Q) * (sizeof(uint32_t) + rb) + (256 * ntiles + 256) * sizeof(uint32_t) + 512;
 }
 
-// Sorts query slots by Morton code (top sort_bits bits).  perm_out receives
-// slot -> caller row.  ws must hold sort_scratch_bytes(Q).  When sort_bits == 0
-// perm_out is not written and false is returned (identity order).
-kd_status morton_sort(kd_tree t, const float* queries, int64_t Q, int sort_bits, void* ws, hipStream_t st,
-                      const uint32_t** perm_out) {
-    *perm_out = nullptr;
-    if (sort_bits <= 0 || Q <= 1) return KD_OK;
+kd_status reorder_queries(kd_tree t, const float* queries, int64_t Q, int sort_bits, void* ws, void* sq,
+                          uint32_t* zero, uint32_t nzero, hipStream_t st) {
     const uint32_t n = uint32_t(Q);
-    const uint32_t ntiles = uint32_t((Q + SORT_TILE - 1) / SORT_TILE);
-    uint32_t* k0 = reinterpret_cast<uint32_t*>(ws);
-    uint32_t* v0 = k0 + Q;
-    uint32_t* k1 = v0 + Q;
-    uint32_t* v1 = k1 + Q;
-    uint32_t* hist = v1 + Q;
-    uint32_t* totals = hist + size_t(256) * ntiles;
-
-    MortonArgs a;
-    a.queries = queries;
-    a.Q = n;
-    a.D = t->dim;
+    SortPass p = {};
+    p.rec = sq;
+    p.n = n;
+    p.zero = zero;
+    p.nzero = nzero;
+    p.m.queries = queries;
+    p.m.Q = n;
     const int bits = t->dim == 2 ? 16 : (t->dim == 3 ? 10 : 8);
     for (int j = 0; j < 4; ++j) {
         const float ext = t->hi[j] - t->lo[j];
-        a.lo[j] = t->lo[j];
-        a.scale[j] = (j < t->dim && ext > 0.0f) ? float(1u << bits) / ext : 0.0f;
+        p.m.lo[j] = t->lo[j];
+        p.m.scale[j] = (j < t->dim && ext > 0.0f) ? float(1u << bits) / ext : 0.0f;
     }
-    hipLaunchKernelGGL(morton_codes, dim3((n + 255) / 256), dim3(256), 0, st, a, k0, v0);
-    KD_HIP(hipGetLastError());
-    const int passes = sort_bits / 8;
-    for (int p = 0; p < passes; ++p) {
-        const int shift = 32 - sort_bits + 8 * p;
-        hipLaunchKernelGGL(radix_hist, dim3(ntiles), dim3(SORT_THREADS), 0, st, k0, n, shift, hist, ntiles);
-        hipLaunchKernelGGL(radix_scan, dim3(256), dim3(SORT_THREADS), 0, st, hist, ntiles, totals);
-        hipLaunchKernelGGL(radix_scatter, dim3(ntiles), dim3(SORT_THREADS), 0, st, k0, v0, n, shift, hist,
-                           ntiles, totals, k1, v1);
+    if (sort_bits <= 0 || n <= 1) {
+        const uint32_t m = n > nzero ? n : nzero;
+        const dim3 g((m + 255) / 256), b(256);
+        if (m == 0) return KD_OK;
+        switch (t->dim) {
+            case 2: hipLaunchKernelGGL(copy_records<2>, g, b, 0, st, p); break;
+            case 3: hipLaunchKernelGGL(copy_records<3>, g, b, 0, st, p); break;
+            default: hipLaunchKernelGGL(copy_records<4>, g, b, 0, st, p); break;
+        }
         KD_HIP(hipGetLastError());
-        uint32_t* tk = k0; k0 = k1; k1 = tk;
-        uint32_t* tv = v0; v0 = v1; v1 = tv;
+        return KD_OK;
     }
-    *perm_out = v0;
+    p.ntiles = sort_tiles(n);
+    const size_t rb = t->dim == 4 ? 32 : 16;
+    char* w = static_cast<char*>(ws);
+    void* r0 = w;
+    void* r1 = w + size_t(n) * rb;
+    uint32_t* k0 = reinterpret_cast<uint32_t*>(w + 2 * size_t(n) * rb);
+    uint32_t* k1 = k0 + n;
+    p.hist = k1 + n;
+    p.totals = p.hist + size_t(256) * p.ntiles;
+    const int passes = sort_bits / 8;
+    for (int q = 0; q < passes; ++q) {
+        p.shift = 32 - sort_bits + 8 * q;
+        p.kin = k0;
+        p.rin = r0;
+        p.kout = k1;
+        p.rout = r1;
+        const bool first = q == 0, last = q == passes - 1;
+        hipError_t e = t->dim == 2 ? launch_pass<2>(p, first, last, st)
+                     : t->dim == 3 ? launch_pass<3>(p, first, last, st) : launch_pass<4>(p, first, last, st);
+        KD_HIP(e);
+        p.zero = nullptr;
+        p.nzero = 0;
+        uint32_t* tk = k0; k0 = k1; k1 = tk;
+        void* tr = r0; r0 = r1; r1 = tr;
+    }
     return KD_OK;
 }
 

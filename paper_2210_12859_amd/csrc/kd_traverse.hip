@@ -48,11 +48,6 @@
 
 #include "kd_internal.h"
 
-// Compile-time variants (results identical; speed differs): prefetch both
-// children of the current node in the same trip.
-#ifndef KD_CHILD_PREFETCH
-#define KD_CHILD_PREFETCH 0
-#endif
 
 namespace kd {
 
@@ -131,52 +126,6 @@ __device__ __forceinline__ void load_tree(const TreeRec<D>* p, float (&c)[D], in
     if (RW == 8) {
         const uint4 hi = reinterpret_cast<const uint4*>(p)[1];
         w[4] = hi.x; w[5] = hi.y; w[6] = hi.z; w[7] = hi.w;
-    }
-#pragma unroll
-    for (int j = 0; j < D; ++j) c[j] = __uint_as_float(w[j]);
-    idx = int32_t(w[D]);
-    anc[0] = 0.0f;
-#pragma unroll
-    for (int j = 0; j < rec_ancestors(D); ++j) anc[j] = __uint_as_float(w[D + 1 + j]);
-}
-
-// Raw record words (RW/4 vectors) and their decoding.
-template <int D>
-struct RawRec {
-    uint4 v[rec_words(D) / 4];
-};
-
-template <int D>
-__device__ __forceinline__ RawRec<D> load_raw(const TreeRec<D>* p) {
-    RawRec<D> r;
-#pragma unroll
-    for (int i = 0; i < rec_words(D) / 4; ++i) r.v[i] = reinterpret_cast<const uint4*>(p)[i];
-    return r;
-}
-
-template <int D>
-__device__ __forceinline__ RawRec<D> select_raw(bool second, const RawRec<D>& a, const RawRec<D>& b) {
-    RawRec<D> r;
-#pragma unroll
-    for (int i = 0; i < rec_words(D) / 4; ++i) {
-        r.v[i].x = second ? b.v[i].x : a.v[i].x;
-        r.v[i].y = second ? b.v[i].y : a.v[i].y;
-        r.v[i].z = second ? b.v[i].z : a.v[i].z;
-        r.v[i].w = second ? b.v[i].w : a.v[i].w;
-    }
-    return r;
-}
-
-template <int D>
-__device__ __forceinline__ void decode_raw(const RawRec<D>& r, float (&c)[D], int32_t& idx,
-                                           float (&anc)[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1]) {
-    uint32_t w[8];
-#pragma unroll
-    for (int i = 0; i < rec_words(D) / 4; ++i) {
-        w[4 * i + 0] = r.v[i].x;
-        w[4 * i + 1] = r.v[i].y;
-        w[4 * i + 2] = r.v[i].z;
-        w[4 * i + 3] = r.v[i].w;
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) c[j] = __uint_as_float(w[j]);
@@ -442,8 +391,6 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
     uint32_t cpos = 0, cn = 0;
 
     Lane<D, K> s;
-    RawRec<D> pf0, pf1;     // prefetched children of node pf_parent
-    int32_t pf_parent = -1;
     bool active = false;
     for (;;) {
         const uint64_t need = __ballot(!active);
@@ -491,28 +438,7 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
             float c[D];
             int32_t idx;
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
-            if (KD_CHILD_PREFETCH) {
-                // The records of curr's two children are requested in the same
-                // trip as curr's own (they sit in one aligned pair), so a
-                // descent finds its next node already in registers.
-                const int32_t cur = s.curr;
-                const bool have = (cur >> 1) == pf_parent;
-                RawRec<D> own;
-                if (!have) own = load_raw<D>(g1 + cur);
-                RawRec<D> n0, n1;
-                const bool kids = 2 * cur <= a.N;
-                if (kids) {
-                    n0 = load_raw<D>(g1 + 2 * cur);
-                    n1 = load_raw<D>(g1 + 2 * cur + 1);
-                }
-                if (have) own = select_raw<D>(cur & 1, pf0, pf1);
-                decode_raw<D>(own, c, idx, anc);
-                pf0 = n0;
-                pf1 = n1;
-                pf_parent = kids ? cur : -1;
-            } else {
-                load_tree<D>(g1 + s.curr, c, idx, anc);
-            }
+            load_tree<D>(g1 + s.curr, c, idx, anc);
             const int32_t next = lane_step<D, K, F>(s, c, idx, anc, a.N);
             if (next == 0) {
                 if (LEARNED && lane_needs_restart<D, K>(s, a.R2)) {
@@ -529,19 +455,6 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
 }
 
 // sq[slot] = (queries[row], row), row = perm[slot] (identity when perm is NULL)
-template <int D>
-__global__ void gather_queries(const float* __restrict__ queries, const uint32_t* __restrict__ perm, uint32_t Q,
-                               NodeRec<D>* __restrict__ sq) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Q) return;
-    const uint32_t row = perm ? perm[i] : i;
-    NodeRec<D> r;
-#pragma unroll
-    for (int j = 0; j < D; ++j) r.c[j] = queries[size_t(row) * D + j];
-    r.idx = int32_t(row);
-    sq[i] = r;
-}
-
 __global__ void zero_u32(uint32_t* p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -609,16 +522,6 @@ size_t rec_bytes(int D) {
         case 3: return sizeof(NodeRec<3>);
         default: return sizeof(NodeRec<4>);
     }
-}
-
-hipError_t launch_gather(int D, const float* queries, const uint32_t* perm, uint32_t Q, void* sq, hipStream_t st) {
-    const dim3 grid((Q + 255) / 256), block(256);
-    switch (D) {
-        case 2: hipLaunchKernelGGL(gather_queries<2>, grid, block, 0, st, queries, perm, Q, (NodeRec<2>*)sq); break;
-        case 3: hipLaunchKernelGGL(gather_queries<3>, grid, block, 0, st, queries, perm, Q, (NodeRec<3>*)sq); break;
-        default: hipLaunchKernelGGL(gather_queries<4>, grid, block, 0, st, queries, perm, Q, (NodeRec<4>*)sq); break;
-    }
-    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ batched jobs
@@ -910,11 +813,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     // scratch: [range cursors | restart count] queries  sort  worst0
     const size_t head = 72 * 1024;
     const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
-    // sort_bits <= 16: one counting sort whose scatter is the gather; more
-    // bits: stable radix sort, then gather
-    const bool bucket = plan.sort_bits > 0 && plan.sort_bits <= 16;
-    const size_t sort_bytes = bucket ? bucket_scratch_bytes(Q, plan.sort_bits)
-                                     : (plan.sort_bits > 0 ? sort_scratch_bytes(Q) : 0);
+    const size_t sort_bytes = plan.sort_bits > 0 ? sort_scratch_bytes(Q, t->dim) : 0;
     const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
     const size_t learn_bytes = learned ? q4 : 0;
     kd_status s = scratch(stream, head + sq_bytes + sort_bytes + learn_bytes, &ws);
@@ -927,24 +826,13 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     float* worst0 = learned ? reinterpret_cast<float*>(base + head + sq_bytes + sort_bytes) : nullptr;
     const uint32_t n_counters = 16 * 1024 + 1;  // range cursors and the restart count
 
-    // query reorder: Morton sort, then gather into traversal order
+    // query reorder: Morton sort whose last pass writes the traversal records
     hipEvent_t evs;
     s = timing_begin(st, &evs);
     if (s != KD_OK) return s;
     hipError_t e = hipSuccess;
-    if (bucket) {
-        s = bucket_sort_gather(t, queries, Q, plan.sort_bits, sort_ws, sq, counter1, n_counters, st);
-        if (s != KD_OK) return s;
-    } else {
-        const uint32_t* perm = nullptr;
-        s = morton_sort(t, queries, Q, plan.sort_bits, sort_ws, st, &perm);
-        if (s != KD_OK) return s;
-        e = launch_gather(t->dim, queries, perm, uint32_t(Q), sq, st);
-        if (e != hipSuccess) return hip_error(e, "gather_queries launch");
-        hipLaunchKernelGGL(zero_u32, dim3(unsigned((n_counters + 255) / 256)), dim3(256), 0, st, counter1,
-                           int(n_counters));
-        KD_HIP(hipGetLastError());
-    }
+    s = reorder_queries(t, queries, Q, plan.sort_bits, sort_ws, sq, counter1, n_counters, st);
+    if (s != KD_OK) return s;
     s = timing_end(st, evs, "sort");
     if (s != KD_OK) return s;
 

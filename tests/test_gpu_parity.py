@@ -89,7 +89,8 @@ def test_c1_knn_entry_without_d2(c1, oracle_lib):
 @pytest.mark.parametrize("opts", [
     dict(block=64), dict(block=128), dict(block=256), dict(block=512), dict(block=1024),
     dict(block=64, waves_per_cu=2), dict(block=256, waves_per_cu=32), dict(block=1024, waves_per_cu=32),
-    dict(sort_bits=0), dict(sort_bits=8), dict(sort_bits=16), dict(sort_bits=24),
+    dict(sort_bits=0), dict(sort_bits=1), dict(sort_bits=8), dict(sort_bits=12), dict(sort_bits=14),
+    dict(sort_bits=15), dict(sort_bits=16), dict(sort_bits=24), dict(sort_bits=32),
 ])
 def test_c1_all_launch_options_identical(c1, oracle_lib, opts):
     P, Qs, tree, order = c1
