@@ -210,7 +210,7 @@ def main():
 
     alg_bytes = visited_total * D * 4  # node data touched per launch
     achieved = alg_bytes / (kern_avg_ms / 1e3) / 1e9
-    cur_hash = src_hash(["paper_2210_12859_amd/csrc/kd_traverse.hip"])
+    cur_hash = src_hash(["paper_2210_12859_amd/csrc/kd_traverse.hip", "paper_2210_12859_amd/csrc/kd_internal.h"])
     traffic = load_traffic(f"traverse_{args.workload}_k{k}", cur_hash, 1)
 
     out = {

@@ -115,19 +115,22 @@ namespace {
 // allocation.
 template <int D>
 void pack_records(const float* pts, const int32_t* order, int64_t N, std::vector<unsigned char>& out) {
-    out.assign(size_t(N + 2) * sizeof(TreeRec<D>), 0);
+    out.assign(node_buffer_bytes(D, N), 0);
     TreeRec<D>* r = reinterpret_cast<TreeRec<D>*>(out.data());
+    int32_t* ids = reinterpret_cast<int32_t*>(r + (N + 2));  // used when the record holds no index
+    constexpr int A0 = D + (rec_has_idx(D) ? 1 : 0);          // first ancestor word
     for (int64_t pos = 0; pos < N; ++pos) {
         TreeRec<D>& rec = r[pos + 1];
         const int32_t i = order[pos];
         for (int j = 0; j < D; ++j) std::memcpy(&rec.w[j], &pts[int64_t(i) * D + j], 4);
-        rec.w[D] = uint32_t(i);
+        if (rec_has_idx(D)) rec.w[D] = uint32_t(i);
+        else ids[pos + 1] = i;
         // ancestors by 1-based id: a = (pos+1) >> m, level floor(log2 a)
         int64_t a = (pos + 1) >> 1;
         for (int m = 0; m < rec_ancestors(D); ++m, a >>= 1) {
             if (a < 1) break;
             const int lvl = 63 - __builtin_clzll((unsigned long long)a);
-            std::memcpy(&rec.w[D + 1 + m], &pts[int64_t(order[a - 1]) * D + (lvl % D)], 4);
+            std::memcpy(&rec.w[A0 + m], &pts[int64_t(order[a - 1]) * D + (lvl % D)], 4);
         }
     }
 }

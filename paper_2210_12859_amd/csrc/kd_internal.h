@@ -23,18 +23,31 @@ struct alignas(16) NodeRec {
 };
 
 // Tree node record: RW = rec_words(D) 32-bit words per level-order position:
-// w[0..D-1] the coordinates, w[D] the caller index, then the split values of
-// the RW - D - 1 nearest ancestors, parent first (the coordinate of the
+// w[0..D-1] the coordinates, then (D = 2, 4) w[D] the caller index, then the
+// split values of the nearest ancestors, parent first (the coordinate of the
 // ancestor's point in that ancestor's split dimension).  Ancestor splits let
 // a lane resolve "return to parent" steps of the traversal from the record it
-// already holds, without loading the parent.  D = 2 uses 16-byte records
-// (one ancestor); D = 3 and D = 4 use 32-byte records (four and three
-// ancestors), loaded as two dwordx4 from one cache line.
+// already holds, without loading the parent.
+//   D = 2: 16 bytes {x, y, index, parent split}
+//   D = 3: 16 bytes {x, y, z, parent split}; the caller index lives in a
+//          separate int32 array after the records (node buffer = records
+//          [N + 2], then indices [N + 2]), read only when a point can enter
+//          the k-best list, so a traversal step is one dwordx4 load
+//   D = 4: 32 bytes {x, y, z, w, index, 3 ancestor splits}
+#ifndef KD_IDX_SPLIT_D3
+#define KD_IDX_SPLIT_D3 1
+#endif
 #ifndef KD_REC_WORDS_D3
 #define KD_REC_WORDS_D3 8
 #endif
-constexpr int rec_words(int D) { return D == 2 ? 4 : (D == 3 ? KD_REC_WORDS_D3 : 8); }
-constexpr int rec_ancestors(int D) { return rec_words(D) - D - 1; }
+constexpr bool rec_has_idx(int D) { return !(D == 3 && KD_IDX_SPLIT_D3); }
+constexpr int rec_words(int D) { return D == 2 ? 4 : (D == 3 ? (KD_IDX_SPLIT_D3 ? 4 : KD_REC_WORDS_D3) : 8); }
+constexpr int rec_ancestors(int D) { return rec_words(D) - D - (rec_has_idx(D) ? 1 : 0); }
+// node buffer bytes for N points (records, then the index array if separate)
+inline size_t node_buffer_bytes(int D, int64_t N) {
+    const size_t recs = size_t(N + 2) * 4 * size_t(rec_words(D));
+    return rec_has_idx(D) ? recs : recs + size_t(N + 2) * 4;
+}
 
 template <int D>
 struct alignas(4 * rec_words(D)) TreeRec {
@@ -57,7 +70,8 @@ struct kd_tree_s {
     int device = 0;
     float lo[4] = {0, 0, 0, 0};
     float hi[4] = {0, 0, 0, 0};
-    void* d_nodes = nullptr;       // TreeRec<dim>[N + 2]: record of node id i at index i
+    void* d_nodes = nullptr;       // node buffer: TreeRec<dim>[N + 2], record of node id i at index i
+                                   // (+ int32 index[N + 2] when the record holds no index)
     std::vector<int32_t> order;    // host copy: order[pos] = caller index
     std::mutex tune_mu;
     std::vector<kd::TuneEntry> tuned;

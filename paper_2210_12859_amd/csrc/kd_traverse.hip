@@ -36,8 +36,10 @@
 //   * each wave pulls 64 queries at a time with one coalesced load and hands
 //     them to idle lanes by cross-lane shuffle, so a lane restarts without a
 //     memory round trip;
-//   * nodes are 16-byte records (D = 2: one dwordx4) or 32-byte records
-//     (D = 3, 4: two dwordx4 from one cache line);
+//   * a step loads one 16-byte record (D = 2, 3: one dwordx4) or a 32-byte
+//     record (D = 4: two dwordx4 from one cache line); with D = 3 the caller
+//     index is read from its own array, only for points that can enter the
+//     k-best list;
 //   * the k-best list lives in VGPRs as 64-bit keys (d2 bits << 32 | index),
 //     so the lexicographic (d2, index) order is one unsigned compare (d2 >= 0,
 //     and the bit pattern of a non-negative float is monotone); insertion is
@@ -73,6 +75,11 @@ struct TravArgs {
     uint8_t* fb_flag;        // [Q] caller order, 1 = restarted from R2 (nullable)
 };
 
+// Wave votes on a lane predicate held as a lane mask (no round trip through
+// a VGPR, as the int-argument forms take).
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
 __device__ __forceinline__ uint64_t make_key(float d2, int32_t idx) {
     return (uint64_t(__float_as_uint(d2)) << 32) | uint32_t(idx);
 }
@@ -91,29 +98,45 @@ __device__ __forceinline__ void list_insert(uint64_t (&L)[K], uint64_t key) {
     L[0] = key < L[0] ? key : L[0];
 }
 
-template <int D>
-__device__ __forceinline__ int dim_up(int d) { return d == 0 ? D - 1 : d - 1; }
-template <int D>
-__device__ __forceinline__ int dim_down(int d) { return d == D - 1 ? 0 : d + 1; }
-
-// v[(dim - I) mod D] as a chain of selects on compile-time constants (a
-// dynamically indexed local array would be placed in LDS by the compiler).
-template <int D, int I>
-__device__ __forceinline__ float sel_rot(float v0, float v1, float v2, float v3, int dim) {
-    // dim == (j + I) mod D picks v_j
-    constexpr int j0 = (D - I % D) % D;  // the pick for dim == 0
-    float r = j0 == 0 ? v0 : (j0 == 1 ? v1 : (j0 == 2 ? v2 : v3));
-    if ((1 + I) % D != 0) r = dim == (1 + I) % D ? v1 : r;
-    if (D > 2 && (2 + I) % D != 0) r = dim == (2 + I) % D ? v2 : r;
-    if (D > 3 && (3 + I) % D != 0) r = dim == (3 + I) % D ? v3 : r;
-    if ((0 + I) % D != 0) r = dim == (0 + I) % D ? v0 : r;
-    return r;
+// Split dimension of node id n (1-based) is level mod D with level =
+// 31 - clz(n).  DimSel holds the one-hot flags dim == j (j = 1..D-1), read
+// as bit clz(n) of compile-time patterns: no division on the step path.
+constexpr uint32_t dim_pattern(int D, int j) {
+    uint32_t p = 0;
+    for (int c = 0; c < 32; ++c)
+        if ((31 - c) % D == j) p |= 1u << c;
+    return p;
 }
 
-template <int D, int I>
-__device__ __forceinline__ float sel_rot(const float (&v)[D], int dim) {
-    return sel_rot<D, I>(v[0], v[1], D > 2 ? v[D > 2 ? 2 : 0] : 0.0f, D > 3 ? v[D > 3 ? 3 : 0] : 0.0f, dim);
-}
+template <int D>
+struct DimSel {
+    bool f[4];  // f[j]: dim == j (f[0] unused)
+    __device__ __forceinline__ explicit DimSel(int32_t id) {
+        const uint32_t c = uint32_t(__clz(id));
+        f[0] = false;
+#pragma unroll
+        for (int j = 1; j < 4; ++j) f[j] = j < D ? __builtin_amdgcn_ubfe(dim_pattern(D, j), c, 1) != 0 : false;
+    }
+    // v[(dim - I) mod D] as a chain of D - 1 selects between values (the
+    // values are passed one by one: a select between elements of a local
+    // array is turned into an indexed access, which lives in LDS/scratch)
+    template <int J>
+    static __device__ __forceinline__ float pick(float v0, float v1, float v2, float v3) {
+        return J == 0 ? v0 : (J == 1 ? v1 : (J == 2 ? v2 : v3));
+    }
+    template <int I>
+    __device__ __forceinline__ float rot(float v0, float v1, float v2, float v3) const {
+        float r = pick<(D - I % D) % D>(v0, v1, v2, v3);
+        if (D > 1) r = f[1] ? pick<(1 - I % D + D) % D>(v0, v1, v2, v3) : r;
+        if (D > 2) r = f[2] ? pick<(2 - I % D + D) % D>(v0, v1, v2, v3) : r;
+        if (D > 3) r = f[3] ? pick<(3 - I % D + D) % D>(v0, v1, v2, v3) : r;
+        return r;
+    }
+    template <int I>
+    __device__ __forceinline__ float rot(const float (&v)[D]) const {
+        return rot<I>(v[0], v[1], D > 2 ? v[D > 2 ? 2 : 0] : 0.0f, D > 3 ? v[D > 3 ? 3 : 0] : 0.0f);
+    }
+};
 
 // Whole-record loads: one or two dwordx4 from one aligned record.
 template <int D>
@@ -127,12 +150,19 @@ __device__ __forceinline__ void load_tree(const TreeRec<D>* p, float (&c)[D], in
         const uint4 hi = reinterpret_cast<const uint4*>(p)[1];
         w[4] = hi.x; w[5] = hi.y; w[6] = hi.z; w[7] = hi.w;
     }
+    constexpr int A0 = D + (rec_has_idx(D) ? 1 : 0);
 #pragma unroll
     for (int j = 0; j < D; ++j) c[j] = __uint_as_float(w[j]);
-    idx = int32_t(w[D]);
+    idx = rec_has_idx(D) ? int32_t(w[D]) : 0;
     anc[0] = 0.0f;
 #pragma unroll
-    for (int j = 0; j < rec_ancestors(D); ++j) anc[j] = __uint_as_float(w[D + 1 + j]);
+    for (int j = 0; j < rec_ancestors(D); ++j) anc[j] = __uint_as_float(w[A0 + j]);
+}
+
+// Caller-index array of a node buffer whose records hold no index.
+template <int D>
+__device__ __forceinline__ const int32_t* node_ids(const TreeRec<D>* g1, int32_t N) {
+    return rec_has_idx(D) ? nullptr : reinterpret_cast<const int32_t*>(g1 + (int64_t(N) + 2));
 }
 
 // Query records (16 bytes for D <= 3, 32 for D = 4).
@@ -249,36 +279,49 @@ __device__ __forceinline__ void lane_finish(const Lane<D, K>& s, const TravArgs&
     if (a.visited) a.visited[s.row] = s.vis;
 }
 
-// One loop trip for a lane at node s.curr (record fields c, idx, anc):
-// the state-machine step at curr, then up to F fused "return to parent"
-// steps.  Returns the new curr (0 = traversal finished).
+// One loop trip for a lane at node s.curr (record fields c, idx, anc; ids
+// is the caller-index array when records hold no index): the state-machine
+// step at curr, then up to F fused "return to parent" steps.  Returns the new
+// curr (0 = traversal finished).
 template <int D, int K, int F>
 __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D], int32_t idx,
+                                             const int32_t* __restrict__ ids,
                                              const float (&anc)[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1],
                                              int32_t N) {
     const int32_t curr = s.curr;
-    const int dim = (31 - __clz(curr)) % D;  // level of curr, mod D
+    const DimSel<D> dim(curr);
     float dx[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) dx[j] = s.q[j] - c[j];
-    const float sd = sel_rot<D, 0>(dx, dim);
+    const float sd = dim.template rot<0>(dx);
     const bool from_parent = s.prev < curr;
     // processNode on the first visit: exact binary32 squared distance, left
     // to right (computed branch-free; only the insertion is conditional).
     float d2 = dx[0] * dx[0];
 #pragma unroll
     for (int j = 1; j < D; ++j) d2 = d2 + dx[j] * dx[j];
-    const uint64_t key = make_key(d2, idx);
     s.vis += from_parent ? 1u : 0u;
-    if (from_parent && key < s.L[K - 1]) list_insert<K>(s.L, key);
+    if constexpr (rec_has_idx(D)) {
+        const uint64_t key = make_key(d2, idx);
+        if (from_parent && key < s.L[K - 1]) list_insert<K>(s.L, key);
+    } else {
+        // the index decides only ties with the worst entry: it is read only
+        // when the point can enter the list (d2 <= worst d2)
+        if (from_parent && __float_as_uint(d2) <= uint32_t(s.L[K - 1] >> 32)) {
+            const uint64_t key = make_key(d2, ids[curr]);
+            if (key < s.L[K - 1]) list_insert<K>(s.L, key);
+        }
+    }
 
     const float worst = key_d2(s.L[K - 1]);
     const bool far_in = sd * sd <= worst;
     const int32_t close_c = (curr << 1) | (sd > 0.0f ? 1 : 0);
     const int32_t far_c = close_c ^ 1;
-    const bool close_ok = close_c <= N;
-    const bool go_close = from_parent & close_ok;
-    const bool try_far = (from_parent & !close_ok) | (!from_parent & (s.prev == close_c));
+    const bool go_close = from_parent & (close_c <= N);
+    // the far child is tried when coming from the parent with no close
+    // child, or when coming back from the close child (prev == close_c
+    // implies prev > curr, i.e. not from the parent)
+    const bool try_far = (from_parent & (close_c > N)) | (s.prev == close_c);
     const bool go_far = try_far & far_in & (far_c <= N);
     bool up = !(go_close | go_far);
     int32_t child = curr;        // node being returned from
@@ -293,9 +336,9 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     auto fused = [&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const bool live = up & (anc_id != 0);
-        if (__any(live)) {
+        {
             if (live) {
-                const float sda = sel_rot<D, i + 1>(s.q, dim) - anc[i];
+                const float sda = dim.template rot<i + 1>(s.q) - anc[i];
                 const bool child_is_close = (child & 1) == (sda > 0.0f ? 1 : 0);
                 const int32_t fa = child ^ 1;
                 const bool take_far = child_is_close & (sda * sda <= worst) & (fa <= N);
@@ -378,6 +421,7 @@ constexpr int max_block(int K) { return K >= 32 ? 256 : 1024; }
 template <int D, int K, int F, bool LEARNED>
 __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
     const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);  // indexed by node id
+    const int32_t* __restrict__ ids = node_ids<D>(g1, a.N);
     const NodeRec<D>* __restrict__ sq = reinterpret_cast<const NodeRec<D>*>(a.sq);
 
     const uint32_t lane = __lane_id();
@@ -390,10 +434,13 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
     float chunk_w0 = 0.0f;
     uint32_t cpos = 0, cn = 0;
 
+    // a lane is active while its curr is a node id (curr = 0: no query; the
+    // state machine ends a traversal by stepping to 0)
     Lane<D, K> s;
-    bool active = false;
+    s.curr = 0;
+    uint32_t restarts = 0;  // learned runs restarted from R2 by this lane
     for (;;) {
-        const uint64_t need = __ballot(!active);
+        const uint64_t need = wave_ballot(s.curr == 0);
         if (need && !ws.exhausted) {
             const uint32_t n = __popcll(need);
             const uint32_t rank = __popcll(need & lt_mask);
@@ -402,9 +449,8 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
                 const int src = int(cpos + (rank < take1 ? rank : 0));
                 const NodeRec<D> v = shfl_rec<D>(chunk, src);
                 const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
-                if (!active && rank < take1) {
+                if (s.curr == 0 && rank < take1) {
                     lane_start<D, K, LEARNED>(s, a, v, vw);
-                    active = true;
                 }
             }
             cpos += take1;
@@ -422,9 +468,8 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
                     const int src = int(r2 < take2 ? r2 : 0);
                     const NodeRec<D> v = shfl_rec<D>(chunk, src);
                     const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
-                    if (!active && rank >= take1 && r2 < take2) {
+                    if (s.curr == 0 && rank >= take1 && r2 < take2) {
                         lane_start<D, K, LEARNED>(s, a, v, vw);
-                        active = true;
                     }
                     cpos = take2;
                 } else {
@@ -433,24 +478,29 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
                 }
             }
         }
-        if (!__any(active)) break;
-        if (active) {
+        if (!wave_any(s.curr != 0)) break;
+        if (s.curr != 0) {
             float c[D];
             int32_t idx;
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
             load_tree<D>(g1 + s.curr, c, idx, anc);
-            const int32_t next = lane_step<D, K, F>(s, c, idx, anc, a.N);
+            const int32_t next = lane_step<D, K, F>(s, c, idx, ids, anc, a.N);
             if (next == 0) {
                 if (LEARNED && lane_needs_restart<D, K>(s, a.R2)) {
                     s.fell_back = true;
-                    if (a.fb_count) atomicAdd(a.fb_count, 1u);
+                    ++restarts;
                     lane_reset<D, K>(s, a.k, a.R2);
                 } else {
                     lane_finish<D, K, LEARNED>(s, a);
-                    active = false;
                 }
             }
         }
+    }
+    if (LEARNED && a.fb_count) {
+        // one atomic per wave (all lanes are here: the loop exit is uniform)
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) restarts += __shfl_xor(restarts, m);
+        if (lane == 0 && restarts) atomicAdd(a.fb_count, restarts);
     }
 }
 
@@ -573,6 +623,7 @@ struct BatchArgs {
 template <int D, int K>
 struct JobLane {
     const TreeRec<D>* g1;  // the lane's tree, indexed by node id
+    const int32_t* ids;    // its caller-index array (records without index)
     int32_t N;
     int32_t k;
     int32_t* oi;
@@ -585,6 +636,7 @@ __device__ __forceinline__ void batch_start(Lane<D, K>& s, JobLane<D, K>& j, con
                                             const BRec& r) {
     const BatchJob& J = jobs[r.job];
     j.g1 = reinterpret_cast<const TreeRec<D>*>(J.nodes);
+    j.ids = node_ids<D>(j.g1, J.N);
     j.N = J.N;
     j.k = J.k;
     j.oi = J.out_idx;
@@ -650,19 +702,18 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
     BRec chunk;
     uint32_t cpos = 0, cn = 0;
     Lane<D, K> s;
+    s.curr = 0;  // active while curr != 0, as in the single-tree kernel
     JobLane<D, K> j;
-    bool active = false;
     for (;;) {
-        const uint64_t need = __ballot(!active);
+        const uint64_t need = wave_ballot(s.curr == 0);
         if (need && !ws.exhausted) {
             const uint32_t n = __popcll(need);
             const uint32_t rank = __popcll(need & lt_mask);
             const uint32_t take1 = n < cn - cpos ? n : cn - cpos;
             {
                 const BRec v = shfl_brec(chunk, int(cpos + (rank < take1 ? rank : 0)));
-                if (!active && rank < take1) {
+                if (s.curr == 0 && rank < take1) {
                     batch_start<D, K>(s, j, a.jobs, v);
-                    active = true;
                 }
             }
             cpos += take1;
@@ -675,9 +726,8 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
                     const uint32_t r2 = rank - take1;
                     const uint32_t take2 = n - take1 < cn2 ? n - take1 : cn2;
                     const BRec v = shfl_brec(chunk, int(r2 < take2 ? r2 : 0));
-                    if (!active && rank >= take1 && r2 < take2) {
+                    if (s.curr == 0 && rank >= take1 && r2 < take2) {
                         batch_start<D, K>(s, j, a.jobs, v);
-                        active = true;
                     }
                     cpos = take2;
                 } else {
@@ -686,16 +736,15 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
                 }
             }
         }
-        if (!__any(active)) break;
-        if (active) {
+        if (!wave_any(s.curr != 0)) break;
+        if (s.curr != 0) {
             float c[D];
             int32_t idx;
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
             load_tree<D>(j.g1 + s.curr, c, idx, anc);
-            const int32_t next = lane_step<D, K, F>(s, c, idx, anc, j.N);
+            const int32_t next = lane_step<D, K, F>(s, c, idx, j.ids, anc, j.N);
             if (next == 0) {
                 batch_finish<D, K>(s, j);
-                active = false;
             }
         }
     }
