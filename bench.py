@@ -93,7 +93,7 @@ def bench_learned(kd, datagen, tree, q, oi, od, k, args, plain_visited, plain_ms
     step.  Results are checked identical to the plain results."""
     import torch
     dev = q.device
-    train = torch.from_numpy(datagen.uniform(1 << 20, q.shape[1], 7)).to(dev)
+    train = torch.from_numpy(datagen.training_queries(args.workload, 1 << 20, 7)).to(dev)
     t0 = time.perf_counter()
     model = kd.kd_radius_model_train(tree, train, k, epochs=args.train_epochs, batch=8192, seed=0)
     torch.cuda.synchronize()

@@ -71,7 +71,16 @@ typedef struct {
                         whole byte (8, 16, 24, 32); -1 = default (16) */
     int waves_per_cu;/* persistent grid size in waves per compute unit (capped by
                         occupancy); 0 = default (24) */
+    int heavy_trips; /* a query still unfinished after this many traversal loop
+                        trips is handed to a second kernel in which a whole wave
+                        finishes it (same results; keeps one far-off query from
+                        holding the launch); -1 = never, 0 = default
+                        (KD_DEFAULT_HEAVY_TRIPS).  No hand-off happens when the
+                        per-query visited count is requested, which is the
+                        single-lane traversal's by definition. */
 } kd_opts;
+
+#define KD_DEFAULT_HEAVY_TRIPS 1024
 
 /* ------------------------------------------------------------ tree build */
 
@@ -176,7 +185,9 @@ kd_status kd_knn_learned(kd_tree t, kd_model m, const float* queries, int64_t Q,
 /* The same query with caller radii: r0 is device float32 [Q] in
  * caller order (any value: NaN, negative or +inf means "no initial radius").
  * fell_back (nullable, device uint8 [Q]) receives 1 for queries re-run from
- * R2.  For checking the exact-fallback rule with arbitrary radii. */
+ * R2, and 2 for queries handed to the cooperative kernel (opts.heavy_trips)
+ * before their initial-radius run ended (they are finished from R2).  For
+ * checking the exact-fallback rule with arbitrary radii. */
 kd_status kd_knn_with_radius(kd_tree t, const float* r0, const float* queries, int64_t Q, int k, float maxRadius,
                              int32_t* out_idx, float* out_d2, uint32_t* visited, uint8_t* fell_back,
                              const kd_opts* opts, kd_stream stream);

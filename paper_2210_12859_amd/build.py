@@ -23,15 +23,18 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libkdtree.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# (source, compiled for the device, extra flags)
 SOURCES = [
-    ("kd_api.cpp", True),
-    ("kd_build_host.cpp", False),
-    ("kd_traverse.hip", True),
-    ("kd_sort.hip", True),
-    ("kd_mlp.hip", True),
-    ("kd_model.cpp", True),
-    ("kd_batch.cpp", True),
-    ("kd_autotune.cpp", True),
+    ("kd_api.cpp", True, []),
+    ("kd_build_host.cpp", False, []),
+    ("kd_traverse.hip", True, []),
+    ("kd_sort.hip", True, []),
+    # matrix-core results in ordinary VGPRs (the MLP kernels read every
+    # accumulator back on the vector ALU; no accumulator-register copies)
+    ("kd_mlp.hip", True, ["-mllvm", "-amdgpu-mfma-vgpr-form"]),
+    ("kd_model.cpp", True, []),
+    ("kd_batch.cpp", True, []),
+    ("kd_autotune.cpp", True, []),
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",
@@ -40,11 +43,11 @@ DEVICE = ["--offload-arch=gfx950", "-fno-gpu-flush-denormals-to-zero", "-fno-gpu
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src: str, is_hip: bool) -> str:
+def _compile(src: str, is_hip: bool, extra: list) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC, *COMMON]
     if is_hip:
-        cmd += ["-x", "hip", *DEVICE]
+        cmd += ["-x", "hip", *DEVICE, *extra]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

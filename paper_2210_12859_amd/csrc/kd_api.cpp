@@ -209,7 +209,7 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     p.K = k_template(k);
     float r = maxRadius;
     p.R2 = r * r;  // binary32 product; +inf stays +inf
-    kd_opts use{0, -1, -1, 0};
+    kd_opts use{0, -1, -1, 0, 0};
     kd_opts tuned;
     if (o) use = *o;
     else if (t && tuned_opts(t, p.K, &tuned)) use = tuned;
@@ -217,6 +217,8 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     if (use.lds_levels < 0) use.lds_levels = 0;
     if (use.sort_bits < 0) use.sort_bits = 16;
     if (use.waves_per_cu == 0) use.waves_per_cu = 24;
+    if (use.heavy_trips == 0) use.heavy_trips = KD_DEFAULT_HEAVY_TRIPS;
+    if (use.heavy_trips < -1) return set_error(KD_EINVAL, "opts.heavy_trips must be -1, 0 or positive");
     if (use.block != 64 && use.block != 128 && use.block != 256 && use.block != 512 && use.block != 1024)
         return set_error(KD_EINVAL, "opts.block must be 64, 128, 256, 512 or 1024");
     if (use.lds_levels > 13) return set_error(KD_EINVAL, "opts.lds_levels must be <= 13");
@@ -227,6 +229,7 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     p.lds_levels = use.lds_levels;
     p.sort_bits = use.sort_bits;
     p.waves_per_cu = use.waves_per_cu;
+    p.heavy_trips = use.heavy_trips > 0 ? use.heavy_trips : 0;
     return KD_OK;
 }
 

@@ -63,7 +63,7 @@ kd_status kd_autotune(kd_tree t, const float* sample_q, int64_t Qs, int k, float
     for (int b : blocks) {
         if (K >= 32 && b > 256) continue;
         for (int w : waves)
-            for (int sb : sorts) cands.push_back(kd_opts{b, 0, sb, w});
+            for (int sb : sorts) cands.push_back(kd_opts{b, 0, sb, w, 0});
     }
     int32_t* idx = nullptr;
     float* d2 = nullptr;

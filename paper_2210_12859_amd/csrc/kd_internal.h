@@ -125,6 +125,7 @@ struct QueryPlan {
     int lds_levels = 10;
     int sort_bits = 32;
     int waves_per_cu = 8;
+    int heavy_trips = 0;  // trip budget before the cooperative hand-off, 0 = none
 };
 int k_template(int k);
 

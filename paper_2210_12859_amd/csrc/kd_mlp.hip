@@ -70,14 +70,6 @@ struct TrainSmem {
     uint64_t a1pos[HID];
 };
 
-constexpr int INFER_WAVES = 4;
-struct InferSmem {
-    uint16_t w2[HID * HID];
-    uint16_t h1[INFER_WAVES][HID * HID];
-    uint16_t h2[INFER_WAVES][HID * HID];
-    uint64_t a1pos[INFER_WAVES][HID];
-};
-
 // Orders this wave's LDS writes before its later LDS reads by other lanes.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -185,30 +177,171 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 // ---------------------------------------------------------------- kernels
 
+// ------------------------------------------------------------ inference
+//
+// Register-resident forward for 64 queries per wave and tile, no LDS.  Both
+// layers run transposed on the matrix cores, queries along N:
+//   GEMM1  a1^T[i][q] = W1b[i][x] . X^T[x][q] + b1[i]    (K = 3, zero-padded to 32)
+//   GEMM2  a2^T[o][q] = W2b[o][i] . h1^T[i][q] + b2[o]   (K = 64, two 32-slices)
+// with the biases preloaded as the accumulators.  GEMM1's output layout
+// (lane l holds rows i = 16 mi + 4 (l/16) + r, r = 0..3, of column q) is fed
+// to GEMM2 directly as its B operand by ordering GEMM2's contraction index:
+// slice kk, element e of lane l's fragment is hidden unit
+//   i = 16 (2 kk + e/4) + 4 (l/16) + e%4,
+// and W2b's fragments use the same order (a contraction does not depend on
+// the order of its index).  Layer 3 is a per-lane bfloat16 dot product over
+// the 16 outputs a lane holds plus two cross-lane sums.  Weights are read
+// into registers once per wave.
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(2))) short s16x2;
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+    const bf16x2 v = {static_cast<__bf16>(lo), static_cast<__bf16>(hi)};  // round to nearest even
+    return __builtin_bit_cast(uint32_t, v);
+}
+// bf16(relu(.)) of a pair: rounding keeps the sign, so relu is applied to the
+// rounded values as a packed 16-bit integer max with 0 (negative bfloat16
+// patterns, -0 included, are negative int16)
+__device__ __forceinline__ uint32_t pack_bf16_relu(float lo, float hi) {
+    const s16x2 v = __builtin_bit_cast(s16x2, pack_bf16(lo, hi));
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, s16x2{0, 0}));
+}
+
+struct InferWeights {
+    bf16x8 a1[4];      // W1b fragments (lanes 0..15: i = 16 mi + l, x = e < 3; else 0)
+    bf16x8 a2[4][2];   // W2b fragments [mo][kk]
+    f32x4 b1[4];       // b1[16 mi + 4 (l/16) + r]
+    f32x4 b2[4];       // b2[16 mo + 4 (l/16) + r]
+    uint32_t w3[4][2]; // w3b pairs for o = 16 mo + 4 (l/16) + {0,1}, {2,3}
+    float b3;
+};
+
+__device__ __forceinline__ void load_weights(const float* __restrict__ P, int lane, InferWeights& W) {
+    const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) {
+        const int i = 16 * mi + c;
+        uint32_t u[4] = {0u, 0u, 0u, 0u};
+        if (g == 0) {
+            u[0] = pack_bf16(P[OFF_W1 + 3 * i + 0], P[OFF_W1 + 3 * i + 1]);
+            u[1] = pack_bf16(P[OFF_W1 + 3 * i + 2], 0.0f);
+        }
+        W.a1[mi] = __builtin_bit_cast(bf16x8, make_uint4(u[0], u[1], u[2], u[3]));
+        const float4 bb1 = *reinterpret_cast<const float4*>(P + OFF_B1 + 16 * mi + 4 * g);
+        W.b1[mi] = f32x4{bb1.x, bb1.y, bb1.z, bb1.w};
+    }
+#pragma unroll
+    for (int mo = 0; mo < 4; ++mo) {
+        const int o = 16 * mo + c;
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            // e = 0..3: i = 16 (2 kk) + 4 g + e;  e = 4..7: i = 16 (2 kk + 1) + 4 g + e - 4
+            const float* r = P + OFF_W2 + o * HID + 4 * g;
+            const float4 lo = *reinterpret_cast<const float4*>(r + 16 * (2 * kk));
+            const float4 hi = *reinterpret_cast<const float4*>(r + 16 * (2 * kk + 1));
+            W.a2[mo][kk] = __builtin_bit_cast(
+                bf16x8, make_uint4(pack_bf16(lo.x, lo.y), pack_bf16(lo.z, lo.w), pack_bf16(hi.x, hi.y),
+                                   pack_bf16(hi.z, hi.w)));
+        }
+        const float4 bb2 = *reinterpret_cast<const float4*>(P + OFF_B2 + 16 * mo + 4 * g);
+        W.b2[mo] = f32x4{bb2.x, bb2.y, bb2.z, bb2.w};
+        const float4 ww3 = *reinterpret_cast<const float4*>(P + OFF_W3 + 16 * mo + 4 * g);
+        W.w3[mo][0] = pack_bf16(ww3.x, ww3.y);
+        W.w3[mo][1] = pack_bf16(ww3.z, ww3.w);
+    }
+    W.b3 = P[OFF_B3];
+}
+
+// y for the 64 queries of a tile; lanes 0..15 pass the normalised inputs
+// xs[nq] of queries 16 nq + lane (other lanes' xs are ignored).  Returns y of
+// query `lane`.
+__device__ __forceinline__ float mlp_tile(const InferWeights& W, const float (&xs)[4][3], int lane) {
+    const int g = lane >> 4;
+    float y_mine = 0.0f;
+#pragma unroll
+    for (int nq = 0; nq < 4; ++nq) {
+        uint32_t u[4] = {0u, 0u, 0u, 0u};
+        if (g == 0) {
+            u[0] = pack_bf16(xs[nq][0], xs[nq][1]);
+            u[1] = pack_bf16(xs[nq][2], 0.0f);
+        }
+        const bf16x8 bx = __builtin_bit_cast(bf16x8, make_uint4(u[0], u[1], u[2], u[3]));
+        // layer 1: a1^T rows 16 mi + 4 g + r of column q = 16 nq + (lane % 16)
+        f32x4 a1[4];
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) a1[mi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.a1[mi], bx, W.b1[mi], 0, 0, 0);
+        // h1 = bf16(relu(a1)) as GEMM2's B fragments
+        bf16x8 h1[2];
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const f32x4 p = a1[2 * kk], q = a1[2 * kk + 1];
+            h1[kk] = __builtin_bit_cast(bf16x8, make_uint4(pack_bf16_relu(p[0], p[1]), pack_bf16_relu(p[2], p[3]),
+                                                           pack_bf16_relu(q[0], q[1]), pack_bf16_relu(q[2], q[3])));
+        }
+        // layer 2 and the lane's part of layer 3
+        float part = 0.0f;
+#pragma unroll
+        for (int mo = 0; mo < 4; ++mo) {
+            f32x4 a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.a2[mo][0], h1[0], W.b2[mo], 0, 0, 0);
+            a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.a2[mo][1], h1[1], a2, 0, 0, 0);
+            const uint32_t h01 = pack_bf16_relu(a2[0], a2[1]);
+            const uint32_t h23 = pack_bf16_relu(a2[2], a2[3]);
+            part = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, h01), __builtin_bit_cast(bf16x2, W.w3[mo][0]),
+                                                   part, false);
+            part = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, h23), __builtin_bit_cast(bf16x2, W.w3[mo][1]),
+                                                   part, false);
+        }
+        // sum over the four lane groups holding column q
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (g == nq) y_mine = part + W.b3;
+    }
+    return y_mine;
+}
+
+template <bool RECORDS>
+__device__ __forceinline__ void load_tile_x(const void* __restrict__ src, uint32_t n, uint32_t tile, int lane,
+                                            const Norm& nm, float (&xs)[4][3]) {
+#pragma unroll
+    for (int nq = 0; nq < 4; ++nq) {
+        xs[nq][0] = xs[nq][1] = xs[nq][2] = 0.0f;
+        const uint32_t i = tile * 64u + 16u * nq + uint32_t(lane);
+        if (lane < 16 && i < n) {
+            float q[3];
+            if (RECORDS) {
+                const float4 v = static_cast<const float4*>(src)[i];
+                q[0] = v.x;
+                q[1] = v.y;
+                q[2] = v.z;
+            } else {
+                const float* p = static_cast<const float*>(src) + size_t(i) * 3;
+                q[0] = p[0];
+                q[1] = p[1];
+                q[2] = p[2];
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) xs[nq][j] = (q[j] - nm.lo[j]) * nm.inv[j];
+        }
+    }
+}
+
 // Inference: worst0[slot] = min(R2, fl(r0 * r0)), r0 = exp(y + margin);
 // a non-finite or negative r0 leaves R2.  Queries are the traversal-order
-// records (16 bytes: x, y, z, row).  Persistent: each wave loops over
-// 64-query tiles; the workgroup shares one LDS copy of W2b.
-__global__ __launch_bounds__(64 * INFER_WAVES) void mlp_worst0(const float* __restrict__ P, Norm nm, float margin,
-                                                               float R2, const float4* __restrict__ sq, uint32_t Q,
-                                                               float* __restrict__ worst0) {
-    __shared__ InferSmem sm;
-    stage_w2(P, sm.w2, nullptr, threadIdx.x, blockDim.x);
-    __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const MlpBufs B{sm.w2, nullptr, sm.h1[w], nullptr, sm.h2[w], nullptr, nullptr, nullptr, nullptr, sm.a1pos[w]};
+// records (16 bytes: x, y, z, row).  Persistent over 64-query tiles.
+__global__ __launch_bounds__(256) void mlp_worst0(const float* __restrict__ P, Norm nm, float margin, float R2,
+                                                  const float4* __restrict__ sq, uint32_t Q,
+                                                  float* __restrict__ worst0) {
+    const int lane = threadIdx.x & 63;
+    InferWeights W;
+    load_weights(P, lane, W);
     const uint32_t ntiles = (Q + 63) / 64;
-    for (uint32_t tile = blockIdx.x * INFER_WAVES + w; tile < ntiles; tile += gridDim.x * INFER_WAVES) {
-        const uint32_t slot = tile * 64u + lane;
-        float q[3] = {0.f, 0.f, 0.f};
-        if (slot < Q) {
-            const float4 v = sq[slot];
-            q[0] = v.x;
-            q[1] = v.y;
-            q[2] = v.z;
-        }
-        f32x4 acc[4][4];
-        const float y = mlp_forward(P, nm, q, B, acc, false, lane);
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t tile = wave; tile < ntiles; tile += nwaves) {
+        float xs[4][3];
+        load_tile_x<true>(sq, Q, tile, lane, nm, xs);
+        const float y = mlp_tile(W, xs, lane);
+        const uint32_t slot = tile * 64u + uint32_t(lane);
         if (slot < Q) {
             const float r0 = __expf(y + margin);
             float wv = R2;
@@ -222,25 +355,19 @@ __global__ __launch_bounds__(64 * INFER_WAVES) void mlp_worst0(const float* __re
 }
 
 // Raw forward for tests: y[i] for caller-layout queries [n][3].
-__global__ __launch_bounds__(64 * INFER_WAVES) void mlp_predict(const float* __restrict__ P, Norm nm,
-                                                                const float* __restrict__ qs, uint32_t n,
-                                                                float* __restrict__ y) {
-    __shared__ InferSmem sm;
-    stage_w2(P, sm.w2, nullptr, threadIdx.x, blockDim.x);
-    __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const MlpBufs B{sm.w2, nullptr, sm.h1[w], nullptr, sm.h2[w], nullptr, nullptr, nullptr, nullptr, sm.a1pos[w]};
+__global__ __launch_bounds__(256) void mlp_predict(const float* __restrict__ P, Norm nm, const float* __restrict__ qs,
+                                                   uint32_t n, float* __restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    InferWeights W;
+    load_weights(P, lane, W);
     const uint32_t ntiles = (n + 63) / 64;
-    for (uint32_t tile = blockIdx.x * INFER_WAVES + w; tile < ntiles; tile += gridDim.x * INFER_WAVES) {
-        const uint32_t i = tile * 64u + lane;
-        float q[3] = {0.f, 0.f, 0.f};
-        if (i < n) {
-            q[0] = qs[size_t(i) * 3 + 0];
-            q[1] = qs[size_t(i) * 3 + 1];
-            q[2] = qs[size_t(i) * 3 + 2];
-        }
-        f32x4 acc[4][4];
-        const float yy = mlp_forward(P, nm, q, B, acc, false, lane);
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t tile = wave; tile < ntiles; tile += nwaves) {
+        float xs[4][3];
+        load_tile_x<false>(qs, n, tile, lane, nm, xs);
+        const float yy = mlp_tile(W, xs, lane);
+        const uint32_t i = tile * 64u + uint32_t(lane);
         if (i < n) y[i] = yy;
     }
 }
@@ -428,13 +555,19 @@ Norm make_norm(const float* lo, const float* inv) {
 
 }  // namespace
 
+// Inference grid: workgroups of 4 waves, each wave looping over 64-query
+// tiles (weights are loaded once per wave); at most 768 workgroups, three
+// waves per SIMD at 148 VGPRs on 256 CUs.
+static uint32_t infer_grid(uint32_t n) {
+    const uint32_t tiles = (n + 63) / 64;
+    uint32_t grid = (tiles + 3) / 4;
+    return grid > 768 ? 768 : grid;
+}
+
 hipError_t launch_mlp_worst0(const float* P, const float* lo, const float* inv, float margin, float R2,
                              const void* sq, uint32_t Q, float* worst0, hipStream_t st) {
     if (Q == 0) return hipSuccess;
-    uint32_t tiles = (Q + 63) / 64;
-    uint32_t grid = (tiles + INFER_WAVES - 1) / INFER_WAVES;
-    if (grid > 1024) grid = 1024;
-    hipLaunchKernelGGL(mlp_worst0, dim3(grid), dim3(64 * INFER_WAVES), 0, st, P, make_norm(lo, inv), margin, R2,
+    hipLaunchKernelGGL(mlp_worst0, dim3(infer_grid(Q)), dim3(256), 0, st, P, make_norm(lo, inv), margin, R2,
                        reinterpret_cast<const float4*>(sq), Q, worst0);
     return hipGetLastError();
 }
@@ -442,10 +575,7 @@ hipError_t launch_mlp_worst0(const float* P, const float* lo, const float* inv, 
 hipError_t launch_mlp_predict(const float* P, const float* lo, const float* inv, const float* qs, uint32_t n,
                               float* y, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    uint32_t tiles = (n + 63) / 64;
-    uint32_t grid = (tiles + INFER_WAVES - 1) / INFER_WAVES;
-    if (grid > 1024) grid = 1024;
-    hipLaunchKernelGGL(mlp_predict, dim3(grid), dim3(64 * INFER_WAVES), 0, st, P, make_norm(lo, inv), qs, n, y);
+    hipLaunchKernelGGL(mlp_predict, dim3(infer_grid(n)), dim3(256), 0, st, P, make_norm(lo, inv), qs, n, y);
     return hipGetLastError();
 }
 

@@ -73,6 +73,11 @@ struct TravArgs {
     const float* worst0;     // [Q] initial squared radius per slot
     uint32_t* fb_count;      // queries restarted from R2 (nullable)
     uint8_t* fb_flag;        // [Q] caller order, 1 = restarted from R2 (nullable)
+    // hand-off of long traversals to the cooperative kernel
+    uint32_t heavy_trips;    // trip budget per query, 0 = none
+    uint32_t heavy_cap;      // at most this many rows are handed off
+    uint32_t* heavy_count;   // rows that asked for a hand-off (zero at launch; may exceed heavy_cap)
+    int32_t* heavy_rows;     // [heavy_cap] caller rows handed off
 };
 
 // Wave votes on a lane predicate held as a lane mask (no round trip through
@@ -112,7 +117,7 @@ template <int D>
 struct DimSel {
     bool f[4];  // f[j]: dim == j (f[0] unused)
     __device__ __forceinline__ explicit DimSel(int32_t id) {
-        const uint32_t c = uint32_t(__clz(id));
+        const uint32_t c = uint32_t(__builtin_clz(uint32_t(id)));  // id >= 1
         f[0] = false;
 #pragma unroll
         for (int j = 1; j < 4; ++j) f[j] = j < D ? __builtin_amdgcn_ubfe(dim_pattern(D, j), c, 1) != 0 : false;
@@ -159,6 +164,17 @@ __device__ __forceinline__ void load_tree(const TreeRec<D>* p, float (&c)[D], in
     for (int j = 0; j < rec_ancestors(D); ++j) anc[j] = __uint_as_float(w[A0 + j]);
 }
 
+// Whole-record load at a wave-uniform node id through the scalar data cache
+// (constant address space: the tree is read-only for the whole launch).
+template <int D>
+__device__ __forceinline__ void load_tree_uniform(const TreeRec<D>* g1, int32_t id, float (&c)[D], int32_t& idx) {
+    typedef __attribute__((address_space(4))) const uint32_t CWord;
+    const CWord* w = (const CWord*)(g1 + __builtin_amdgcn_readfirstlane(id));
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = __uint_as_float(w[j]);
+    idx = rec_has_idx(D) ? int32_t(w[D]) : 0;
+}
+
 // Caller-index array of a node buffer whose records hold no index.
 template <int D>
 __device__ __forceinline__ const int32_t* node_ids(const TreeRec<D>* g1, int32_t N) {
@@ -192,6 +208,11 @@ __device__ __forceinline__ NodeRec<D> shfl_rec(const NodeRec<D>& r, int src) {
     return o;
 }
 
+#ifndef KD_FUSED_LEVELS
+#define KD_FUSED_LEVELS 1
+#endif
+constexpr int fused_levels(int D) { return KD_FUSED_LEVELS < rec_ancestors(D) ? KD_FUSED_LEVELS : rec_ancestors(D); }
+
 // Per-lane query state: the two node ids of the state machine (1-based),
 // the split dimension of `curr` (implied by its level, tracked as the lane
 // moves), the query and its k-best list.
@@ -207,6 +228,7 @@ struct Lane {
     int32_t curr, prev;
     int32_t row;
     uint32_t vis;
+    uint32_t trips;    // loop trips spent on the current query
     float w0;          // initial squared radius of the current run
     bool fell_back;    // the learned run found < k points and was restarted
 };
@@ -229,6 +251,7 @@ __device__ __forceinline__ void lane_start(Lane<D, K>& s, const TravArgs& a, con
     for (int j = 0; j < D; ++j) s.q[j] = qr.c[j];
     s.row = qr.idx;
     s.vis = 0;
+    s.trips = 0;
     s.fell_back = false;
     lane_reset<D, K>(s, a.k, LEARNED ? w0 : a.R2);
 }
@@ -283,11 +306,11 @@ __device__ __forceinline__ void lane_finish(const Lane<D, K>& s, const TravArgs&
 // is the caller-index array when records hold no index): the state-machine
 // step at curr, then up to F fused "return to parent" steps.  Returns the new
 // curr (0 = traversal finished).
-template <int D, int K, int F>
+template <int D, int K, int F, bool CAP = false>
 __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D], int32_t idx,
                                              const int32_t* __restrict__ ids,
                                              const float (&anc)[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1],
-                                             int32_t N) {
+                                             int32_t N, float cap = 0.0f, int32_t stop = 0) {
     const int32_t curr = s.curr;
     const DimSel<D> dim(curr);
     float dx[D];
@@ -295,33 +318,37 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     for (int j = 0; j < D; ++j) dx[j] = s.q[j] - c[j];
     const float sd = dim.template rot<0>(dx);
     const bool from_parent = s.prev < curr;
-    // processNode on the first visit: exact binary32 squared distance, left
-    // to right (computed branch-free; only the insertion is conditional).
-    float d2 = dx[0] * dx[0];
+    if (from_parent) {
+        // processNode on the first visit: exact binary32 squared distance,
+        // left to right, and insertion into the k-best list
+        ++s.vis;
+        float d2 = dx[0] * dx[0];
 #pragma unroll
-    for (int j = 1; j < D; ++j) d2 = d2 + dx[j] * dx[j];
-    s.vis += from_parent ? 1u : 0u;
-    if constexpr (rec_has_idx(D)) {
-        const uint64_t key = make_key(d2, idx);
-        if (from_parent && key < s.L[K - 1]) list_insert<K>(s.L, key);
-    } else {
-        // the index decides only ties with the worst entry: it is read only
-        // when the point can enter the list (d2 <= worst d2)
-        if (from_parent && __float_as_uint(d2) <= uint32_t(s.L[K - 1] >> 32)) {
-            const uint64_t key = make_key(d2, ids[curr]);
+        for (int j = 1; j < D; ++j) d2 = d2 + dx[j] * dx[j];
+        if constexpr (rec_has_idx(D)) {
+            const uint64_t key = make_key(d2, idx);
             if (key < s.L[K - 1]) list_insert<K>(s.L, key);
+        } else {
+            // the index decides only ties with the worst entry: it is read
+            // only when the point can enter the list (d2 <= worst d2)
+            if (__float_as_uint(d2) <= uint32_t(s.L[K - 1] >> 32)) {
+                const uint64_t key = make_key(d2, ids[curr]);
+                if (key < s.L[K - 1]) list_insert<K>(s.L, key);
+            }
         }
     }
 
-    const float worst = key_d2(s.L[K - 1]);
+    // CAP: prune with a tighter bound known to be >= the final k-th distance
+    const float worst = CAP ? fminf(key_d2(s.L[K - 1]), cap) : key_d2(s.L[K - 1]);
     const bool far_in = sd * sd <= worst;
     const int32_t close_c = (curr << 1) | (sd > 0.0f ? 1 : 0);
     const int32_t far_c = close_c ^ 1;
-    const bool go_close = from_parent & (close_c <= N);
+    const bool close_missing = close_c > N;
+    const bool go_close = from_parent & !close_missing;
     // the far child is tried when coming from the parent with no close
     // child, or when coming back from the close child (prev == close_c
     // implies prev > curr, i.e. not from the parent)
-    const bool try_far = (from_parent & (close_c > N)) | (s.prev == close_c);
+    const bool try_far = (from_parent & close_missing) | (s.prev == close_c);
     const bool go_far = try_far & far_in & (far_c <= N);
     bool up = !(go_close | go_far);
     int32_t child = curr;        // node being returned from
@@ -335,7 +362,7 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     // keep returning.
     auto fused = [&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        const bool live = up & (anc_id != 0);
+        const bool live = up & (anc_id != stop);  // stop: parent of the traversal's root
         {
             if (live) {
                 const float sda = dim.template rot<i + 1>(s.q) - anc[i];
@@ -485,7 +512,20 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
             load_tree<D>(g1 + s.curr, c, idx, anc);
             const int32_t next = lane_step<D, K, F>(s, c, idx, ids, anc, a.N);
-            if (next == 0) {
+            bool handed = false;
+            if (++s.trips == a.heavy_trips && next != 0) {
+                // over budget: the cooperative kernel finishes this query,
+                // unless it already holds heavy_cap queries (then the lane
+                // goes on; the budget is checked once per query)
+                const uint32_t pos = atomicAdd(a.heavy_count, 1u);
+                if (pos < a.heavy_cap) {
+                    a.heavy_rows[pos] = s.row;
+                    if (LEARNED && a.fb_flag) a.fb_flag[s.row] = s.fell_back ? 1 : 2;
+                    s.curr = 0;
+                    handed = true;
+                }
+            }
+            if (!handed && next == 0) {
                 if (LEARNED && lane_needs_restart<D, K>(s, a.R2)) {
                     s.fell_back = true;
                     ++restarts;
@@ -504,16 +544,207 @@ __global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
     }
 }
 
-// sq[slot] = (queries[row], row), row = perm[slot] (identity when perm is NULL)
+// ------------------------------------------------------------ cooperative
+//
+// Queries whose traversal exceeds the trip budget (a query far from dense
+// data can visit tens of thousands of nodes; one lane would then hold the
+// whole launch) are finished here by a whole wave.  The wave walks the top
+// levels of the tree with the same state machine, wave-uniformly, processing
+// those nodes itself; each node of depth T it steps into is given, with its
+// whole subtree, to an idle lane, and the walk goes on as if returning from
+// it.  A lane runs the same state machine inside its subtree and stops when
+// it steps back out of the subtree root.  The walk and the lanes prune with a
+// wave-wide bound that is never below the final k-th distance of the query
+// (see coop_bound), so every point of the result is still processed, by
+// exactly one lane.  The k best keys of the 64 lists are then merged.  The
+// result (indices and squared distances) equals the single-lane traversal's;
+// the order and number of processed nodes differ.  Subtrees have about
+// 2^KD_COOP_SUB_LEVELS nodes, so a large search spreads over many lanes.
+#ifndef KD_COOP_SUB_LEVELS
+#define KD_COOP_SUB_LEVELS 9
+#endif
+// hand-offs are capped at this many rounds of one query per cooperative wave
+#ifndef KD_COOP_ROUNDS
+#define KD_COOP_ROUNDS 4
+#endif
+struct CoopArgs {
+    const void* nodes;
+    int32_t N;
+    int T;                   // subtree depth: levels - 1 - KD_COOP_SUB_LEVELS, at least 0
+    const float* queries;    // caller [Q][D]
+    int k;
+    float R2;
+    int32_t* out_idx;
+    float* out_d2;
+    const uint32_t* heavy_count;
+    uint32_t heavy_cap;
+    const int32_t* heavy_rows;
+};
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint32_t o = __shfl_xor(v, m);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t o = (uint64_t(uint32_t(__shfl_xor(uint32_t(v >> 32), m))) << 32) |
+                           uint32_t(__shfl_xor(uint32_t(v), m));
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// k-th smallest of the lanes' values (k <= 64), bit by bit from the top:
+// bit b of the answer is 0 iff at least k lanes hold a value <= the answer's
+// upper bits followed by ones.
+__device__ __forceinline__ uint32_t wave_kth_smallest(uint32_t u, int k) {
+    uint32_t r = 0;
+    for (int b = 31; b >= 0; --b) {
+        const uint32_t t = r | ((1u << b) - 1u);
+        if (__popcll(wave_ballot(u <= t)) < k) r |= 1u << b;
+    }
+    return r;
+}
+
+// Pruning bound of the cooperative kernel, >= the query's final k-th
+// distance: the smaller of (a) the lanes' smallest k-th distance and (b)
+// the k-th smallest of the lanes' best distances (k lanes each hold a point
+// at most that far).
+template <int K>
+__device__ __forceinline__ float coop_bound(const uint64_t (&L)[K], int k) {
+    uint32_t best = ~0u;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint32_t v = j >= K - k ? uint32_t(L[j] >> 32) : ~0u;
+        best = v < best ? v : best;
+    }
+    const uint32_t a = wave_min_u32(uint32_t(L[K - 1] >> 32));
+    const uint32_t b = wave_kth_smallest(best, k);
+    return __uint_as_float(a < b ? a : b);
+}
+
+template <int D, int K>
+__global__ __launch_bounds__(256) void knn_coop(CoopArgs a) {
+    const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);
+    const int32_t* __restrict__ ids = node_ids<D>(g1, a.N);
+    const uint32_t lane = __lane_id();
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t nheavy = *a.heavy_count < a.heavy_cap ? *a.heavy_count : a.heavy_cap;
+    const int32_t first_sub = int32_t(1) << a.T;  // ids of depth T: [2^T, 2^(T+1))
+    for (uint32_t h = wave; h < nheavy; h += nwaves) {
+        const int32_t row = a.heavy_rows[h];
+        Lane<D, K> s;
+#pragma unroll
+        for (int j = 0; j < D; ++j) s.q[j] = a.queries[int64_t(row) * D + j];
+        s.row = row;
+        s.vis = 0;
+        lane_reset<D, K>(s, a.k, a.R2);
+        s.curr = 0;
+        int32_t stop = 0;
+        // wave-uniform walk of the top levels (the same state machine); a
+        // depth-T node it steps into goes to an idle lane as a whole subtree
+        int32_t tcurr = 1, tprev = 0;
+        bool top_done = false;
+        float bound = a.R2;
+        uint32_t trip = 0;
+        for (;;) {
+            uint64_t idle = wave_ballot(s.curr == 0);
+            while (idle && !top_done) {
+                if (tcurr == 0) {
+                    top_done = true;
+                    break;
+                }
+                if (tcurr >= first_sub) {
+                    const uint32_t l = uint32_t(__builtin_ctzll(idle));
+                    idle &= idle - 1;
+                    if (lane == l) {
+                        s.curr = tcurr;
+                        s.prev = tcurr >> 1;
+                        stop = tcurr >> 1;
+                    }
+                    tprev = tcurr;
+                    tcurr = tcurr >> 1;
+                    continue;
+                }
+                float c[D];
+                int32_t idx;
+                load_tree_uniform<D>(g1, tcurr, c, idx);
+                const bool from_parent = tprev < tcurr;
+                float dx[D];
+#pragma unroll
+                for (int j = 0; j < D; ++j) dx[j] = s.q[j] - c[j];
+                if (from_parent && lane == 0) {
+                    float d2 = dx[0] * dx[0];
+#pragma unroll
+                    for (int j = 1; j < D; ++j) d2 = d2 + dx[j] * dx[j];
+                    if (__float_as_uint(d2) <= uint32_t(s.L[K - 1] >> 32)) {
+                        const uint64_t key = make_key(d2, rec_has_idx(D) ? idx : ids[tcurr]);
+                        if (key < s.L[K - 1]) list_insert<K>(s.L, key);
+                    }
+                }
+                const DimSel<D> dim(tcurr);
+                const float sd = dim.template rot<0>(dx);
+                const int32_t close_c = (tcurr << 1) | (sd > 0.0f ? 1 : 0);
+                const int32_t far_c = close_c ^ 1;
+                const bool far_ok = far_c <= a.N && sd * sd <= bound;
+                int32_t next;
+                if (from_parent && close_c <= a.N) next = close_c;
+                else if ((from_parent || tprev == close_c) && far_ok) next = far_c;
+                else next = tcurr >> 1;
+                tprev = tcurr;
+                tcurr = __builtin_amdgcn_readfirstlane(next);
+                tprev = __builtin_amdgcn_readfirstlane(tprev);
+            }
+            if (top_done && !wave_any(s.curr != 0)) break;
+            if (s.curr != 0) {
+                float c[D];
+                int32_t idx;
+                float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
+                load_tree<D>(g1 + s.curr, c, idx, anc);
+                lane_step<D, K, fused_levels(D), true>(s, c, idx, ids, anc, a.N, bound, stop);
+                if (s.curr == stop) s.curr = 0;
+            }
+            // the wave-wide bound is refreshed every 8 trips (a stale bound
+            // is larger, so still safe to prune with)
+            if ((++trip & 7u) == 0) bound = coop_bound<K>(s.L, a.k);
+        }
+        // merge: k rounds of the wave-wide smallest key; the lane holding it
+        // (keys of points are unique) drops it.  Slots below K - k hold no
+        // point: they are set to the largest key first.
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < K - a.k) s.L[j] = ~uint64_t(0);
+        for (int r = 0; r < a.k; ++r) {
+            uint64_t head = s.L[0];
+#pragma unroll
+            for (int j = 1; j < K; ++j) head = s.L[j] < head ? s.L[j] : head;
+            const uint64_t m = wave_min_u64(head);
+            const bool empty = uint32_t(m) == SENT_IDX;
+            if (lane == 0) {
+                a.out_idx[int64_t(row) * a.k + r] = empty ? -1 : int32_t(uint32_t(m));
+                if (a.out_d2) a.out_d2[int64_t(row) * a.k + r] = empty ? __builtin_inff() : key_d2(m);
+            }
+            if (!empty && head == m) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    if (s.L[j] == m) s.L[j] = ~uint64_t(0);
+            }
+        }
+    }
+}
+
 __global__ void zero_u32(uint32_t* p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
 }
 
-#ifndef KD_FUSED_LEVELS
-#define KD_FUSED_LEVELS 1
-#endif
-constexpr int fused_levels(int D) { return KD_FUSED_LEVELS < rec_ancestors(D) ? KD_FUSED_LEVELS : rec_ancestors(D); }
 
 template <int D, int K>
 hipError_t launch_knn(const TravArgs& a, bool learned, int block, int grid, hipStream_t st) {
@@ -562,6 +793,31 @@ hipError_t dispatch_dk(int D, int K, const TravArgs& a, bool learned, int block,
         case 2: return dispatch_k<2>(K, a, learned, block, grid, st);
         case 3: return dispatch_k<3>(K, a, learned, block, grid, st);
         case 4: return dispatch_k<4>(K, a, learned, block, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int D>
+hipError_t launch_coop_k(int K, const CoopArgs& a, int grid, hipStream_t st) {
+    const dim3 g(grid), b(256);
+    switch (K) {
+        case 1: hipLaunchKernelGGL((knn_coop<D, 1>), g, b, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((knn_coop<D, 2>), g, b, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((knn_coop<D, 4>), g, b, 0, st, a); break;
+        case 8: hipLaunchKernelGGL((knn_coop<D, 8>), g, b, 0, st, a); break;
+        case 16: hipLaunchKernelGGL((knn_coop<D, 16>), g, b, 0, st, a); break;
+        case 32: hipLaunchKernelGGL((knn_coop<D, 32>), g, b, 0, st, a); break;
+        case 64: hipLaunchKernelGGL((knn_coop<D, 64>), g, b, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_coop(int D, int K, const CoopArgs& a, int grid, hipStream_t st) {
+    switch (D) {
+        case 2: return launch_coop_k<2>(K, a, grid, st);
+        case 3: return launch_coop_k<3>(K, a, grid, st);
+        case 4: return launch_coop_k<4>(K, a, grid, st);
     }
     return hipErrorInvalidValue;
 }
@@ -859,21 +1115,29 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const DeviceInfo& dev = device_info(t->device);
     void* ws = nullptr;
-    // scratch: [range cursors | restart count] queries  sort  worst0
+    // scratch: [range cursors | restart count | hand-off count] queries  sort
+    //          worst0  hand-off rows
+    // The per-query visited count is the single-lane traversal's, so there
+    // is no hand-off when it is requested.
+    const bool handoff = plan.heavy_trips > 0 && visited == nullptr;
     const size_t head = 72 * 1024;
     const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
     const size_t sort_bytes = plan.sort_bits > 0 ? sort_scratch_bytes(Q, t->dim) : 0;
     const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
     const size_t learn_bytes = learned ? q4 : 0;
-    kd_status s = scratch(stream, head + sq_bytes + sort_bytes + learn_bytes, &ws);
+    const size_t heavy_bytes = handoff ? q4 : 0;
+    kd_status s = scratch(stream, head + sq_bytes + sort_bytes + learn_bytes + heavy_bytes, &ws);
     if (s != KD_OK) return s;
     char* base = static_cast<char*>(ws);
     uint32_t* counter1 = reinterpret_cast<uint32_t*>(base);
     uint32_t* fb_count = reinterpret_cast<uint32_t*>(base + 64 * 1024);
+    uint32_t* heavy_count = reinterpret_cast<uint32_t*>(base + 64 * 1024 + 4);
     void* sq = base + head;
     void* sort_ws = base + head + sq_bytes;
     float* worst0 = learned ? reinterpret_cast<float*>(base + head + sq_bytes + sort_bytes) : nullptr;
-    const uint32_t n_counters = 16 * 1024 + 1;  // range cursors and the restart count
+    int32_t* heavy_rows = handoff ? reinterpret_cast<int32_t*>(base + head + sq_bytes + sort_bytes + learn_bytes)
+                                  : nullptr;
+    const uint32_t n_counters = 16 * 1024 + 2;  // range cursors, restart count, hand-off count
 
     // query reorder: Morton sort whose last pass writes the traversal records
     hipEvent_t evs;
@@ -917,6 +1181,14 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
         a.fb_count = fb_count;
         a.fb_flag = learned->fb_flag;
     }
+    const int coop_grid = dev.cus * 2;                      // workgroups of 4 waves
+    const uint32_t heavy_cap = uint32_t(coop_grid) * 4u * KD_COOP_ROUNDS;  // rounds of one query per wave
+    if (handoff) {
+        a.heavy_trips = uint32_t(plan.heavy_trips);
+        a.heavy_cap = heavy_cap;
+        a.heavy_count = heavy_count;
+        a.heavy_rows = heavy_rows;
+    }
 
     int block = plan.block;
     if (plan.K >= 32 && block > 256) block = 256;
@@ -939,6 +1211,31 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     if (e != hipSuccess) return hip_error(e, "knn_persistent launch");
     s = timing_end(st, ev0, "traverse");
     if (s != KD_OK) return s;
+    if (handoff) {
+        // queries over the trip budget, one wave each (the count is read on
+        // the device; waves beyond it exit at once)
+        CoopArgs c = {};
+        c.nodes = t->d_nodes;
+        c.N = int32_t(t->N);
+        int levels = 0;
+        while (levels < 31 && (int64_t(1) << levels) <= t->N) ++levels;  // floor(log2 N) + 1
+        c.T = levels - 1 - KD_COOP_SUB_LEVELS > 0 ? levels - 1 - KD_COOP_SUB_LEVELS : 0;
+        c.queries = queries;
+        c.k = plan.k;
+        c.R2 = plan.R2;
+        c.out_idx = out_idx;
+        c.out_d2 = out_d2;
+        c.heavy_count = heavy_count;
+        c.heavy_cap = heavy_cap;
+        c.heavy_rows = heavy_rows;
+        hipEvent_t evc;
+        s = timing_begin(st, &evc);
+        if (s != KD_OK) return s;
+        e = launch_coop(t->dim, plan.K, c, coop_grid, st);
+        if (e != hipSuccess) return hip_error(e, "knn_coop launch");
+        s = timing_end(st, evc, "coop");
+        if (s != KD_OK) return s;
+    }
     if (fallbacks_out) {
         KD_HIP(hipMemcpyAsync(fallbacks_out, fb_count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         KD_HIP(hipStreamSynchronize(st));

@@ -98,6 +98,18 @@ def job_arrays(job: dict):
             gmm(n, dim, job["query_seed"], center_seed=7 + job["point_seed"]))
 
 
+def training_queries(name: str, n: int = 1 << 20, seed: int = 7) -> np.ndarray:
+    """Queries for training the radius model on a named workload: same
+    distribution as the workload's queries, a different seed."""
+    if name in ("uniform-16k", "uniform-1m"):
+        return uniform(n, 3, seed)
+    if name == "gmm64-1m":
+        return gmm(n, 3, seed)
+    if name == "clustered-10m":
+        return clustered_lr_queries(n, seed)
+    raise KeyError(name)
+
+
 def workload(name: str):
     """(points, queries) for a named workload."""
     if name == "uniform-16k":
