@@ -8,6 +8,10 @@ HBM, outputs preallocated.  The tree is built once, untimed.  Prints ONE JSON
 line.  The roofline figure is for the traversal kernel: algorithmic bytes =
 processed nodes x dim x 4 B (node data touched), divided by the kernel's mean
 duration from hipEvents recorded around each launch on its own stream.
+
+The same line carries the learned-radius variant on the same queries
+("learned"), a batched many-tree measurement ("batched") and the CPU oracle
+timed on the host ("cpu_baseline"); each can be skipped by a flag.
 """
 from __future__ import annotations
 
@@ -137,6 +141,65 @@ def bench_learned(kd, datagen, tree, q, oi, od, k, args, plain_visited, plain_ms
             "epochs": args.train_epochs, "holdout_rmse": info["holdout_rmse"], "margin": info["margin"], **stages}
 
 
+def bench_batched(kd, datagen, args):
+    """Many trees in one captured launch pipeline: jobs drawn like the batched
+    workload (N log-uniform, D in {2,3,4}, uniform or GMM-64, k in {1,8,32},
+    Q = N), trees built untimed.  Timed: kd_batch_run (hipGraph replay of the
+    whole pipeline) per step, against the same jobs as one kd_knn call each.
+    Results are checked identical."""
+    import torch
+    dev = torch.device("cuda:0")
+    jobs_meta = datagen.batched_jobs(args.batch_jobs, seed=42, n_max=args.batch_nmax)
+    jobs, single = [], []
+    t0 = time.perf_counter()
+    for m in jobs_meta:
+        P, Qs = datagen.job_arrays(m)
+        tree = kd.kd_build(torch.from_numpy(P).to(dev))
+        q = torch.from_numpy(Qs).to(dev)
+        Q, k = q.shape[0], m["k"]
+        jobs.append(dict(tree=tree, queries=q, k=k, out_idx=torch.empty((Q, k), dtype=torch.int32, device=dev),
+                         out_d2=torch.empty((Q, k), dtype=torch.float32, device=dev)))
+        single.append((torch.empty((Q, k), dtype=torch.int32, device=dev),
+                       torch.empty((Q, k), dtype=torch.float32, device=dev)))
+    torch.cuda.synchronize()
+    log(f"batched: {len(jobs)} trees built in {time.perf_counter() - t0:.1f}s (untimed)")
+    total_q = sum(j["queries"].shape[0] for j in jobs)
+    batch = kd.Batch(jobs)
+    stream = torch.cuda.current_stream()
+
+    def run_single():
+        for j, (oi, od) in zip(jobs, single):
+            kd.kd_knn(j["tree"], j["queries"], j["k"], out_idx=oi, out_d2=od)
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_b = timed(lambda: batch.run(stream), args.steps)
+    ms_s = timed(run_single, max(1, args.steps // 4))
+    identical = all(torch.equal(j["out_idx"], oi) and torch.equal(j["out_d2"].view(torch.int32), od.view(torch.int32))
+                    for j, (oi, od) in zip(jobs, single))
+    batch.close()
+    for j in jobs:
+        j["tree"].close()
+    log(f"batched: {ms_b:.3f} ms/step ({total_q / ms_b / 1e3:.1f} M queries/s), one call per tree "
+        f"{ms_s:.3f} ms/step, identical {identical}")
+    return {"value": total_q / (ms_b / 1e3), "unit": "queries/s", "ms_per_step": ms_b, "jobs": len(jobs),
+            "total_queries": total_q, "ms_per_step_one_call_per_tree": ms_s, "speedup_vs_one_call_per_tree": ms_s / ms_b,
+            "identical_to_single_calls": identical,
+            "sample": f"{len(jobs)} trees, N log-uniform [1000, {args.batch_nmax}], D in {{2,3,4}}, uniform or "
+                      f"GMM-64, k in {{1,8,32}}, Q = N, seed 42; hipGraph replay per step"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +210,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-radius variant")
     ap.add_argument("--train-epochs", type=int, default=8)
+    ap.add_argument("--batch-jobs", type=int, default=128, help="trees in the batched measurement (0 = skip)")
+    ap.add_argument("--batch-nmax", type=int, default=262144, help="largest tree of the batched measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -238,6 +303,8 @@ def main():
     }
     if not args.no_learned and D == 3:
         out["learned"] = bench_learned(kd, datagen, tree, q, oi, od, k, args, visited_total, ms_per_step)
+    if args.batch_jobs > 0:
+        out["batched"] = bench_batched(kd, datagen, args)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(P, Qs, k)

@@ -154,28 +154,64 @@ kd_status kd_batch_create(const kd_job* jobs, int n_jobs, const kd_opts* opts, k
         if (own) (void)hipStreamDestroy(own);
         return st;
     };
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return fail(hip_error(e, "kd_batch_create: begin capture"));
+    // One graph branch per (dim, K) class: the classes are independent, so
+    // their persistent launches overlap and the long traversals that end one
+    // class run beside the next class's work.  Branch streams use the default
+    // priority; they fork from and join back into the capture stream.
+    std::vector<hipStream_t> side(b->classes.size(), nullptr);
+    std::vector<hipEvent_t> done(b->classes.size(), nullptr);
+    hipEvent_t fork = nullptr;
+    auto release = [&]() {
+        for (hipStream_t x : side)
+            if (x) (void)hipStreamDestroy(x);
+        for (hipEvent_t x : done)
+            if (x) (void)hipEventDestroy(x);
+        if (fork) (void)hipEventDestroy(fork);
+    };
+    hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    for (size_t i = 0; i < side.size() && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        release();
+        return fail(hip_error(e, "kd_batch_create: branch streams"));
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        release();
+        return fail(hip_error(e, "kd_batch_create: begin capture"));
+    }
     for (size_t i = 0; i < b->empty_out.size(); ++i) {
         const int64_t n = b->empty_n[i];
         hipLaunchKernelGGL(batch_fill_empty, dim3(unsigned((n + 255) / 256)), dim3(256), 0, cs,
                            b->empty_out[i].first, b->empty_out[i].second, n);
     }
-    for (auto& c : b->classes) {
-        if (s != KD_OK) break;
+    e = hipEventRecord(fork, cs);
+    for (size_t i = 0; i < b->classes.size() && s == KD_OK && e == hipSuccess; ++i) {
+        auto& c = b->classes[i];
+        hipStream_t bs = side[i];
+        e = hipStreamWaitEvent(bs, fork, 0);
+        if (e != hipSuccess) break;
         char* ws = static_cast<char*>(c.ws);
         const size_t sort_b = (batch_sort_scratch_bytes(c.n) + 255) & ~size_t(255);
         const size_t rec_b = (size_t(c.n) * batch_rec_bytes() + 255) & ~size_t(255);
         const uint32_t* perm = nullptr;
-        s = batch_sort(c.d_jobs, c.njobs, c.dim, c.n, plan.sort_bits, ws, cs, &perm);
+        s = batch_sort(c.d_jobs, c.njobs, c.dim, c.n, plan.sort_bits, ws, bs, &perm);
         if (s != KD_OK) break;
         QueryPlan cp = plan;
         cp.K = c.K;
         s = run_batch_class(c.d_jobs, c.njobs, c.dim, c.K, c.n, perm, ws + sort_b,
-                            reinterpret_cast<uint32_t*>(ws + sort_b + rec_b), cp, device, cs);
+                            reinterpret_cast<uint32_t*>(ws + sort_b + rec_b), cp, device, bs);
+        if (s != KD_OK) break;
+        e = hipEventRecord(done[i], bs);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[i], 0);
     }
     hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(cs, &graph);
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    release();
+    if (s == KD_OK && e != hipSuccess) s = hip_error(e, "kd_batch_create: branch capture");
+    e = ec;
     if (s != KD_OK) {
         if (graph) (void)hipGraphDestroy(graph);
         return fail(s);
