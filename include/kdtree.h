@@ -70,7 +70,7 @@ typedef struct {
                         0 keeps the caller's order; 1..32 is rounded up to a
                         whole byte (8, 16, 24, 32); -1 = default (16) */
     int waves_per_cu;/* persistent grid size in waves per compute unit (capped by
-                        occupancy); 0 = default (24) */
+                        occupancy); 0 = default (32 for fcp / k = 1, else 24) */
     int heavy_trips; /* a query still unfinished after this many traversal loop
                         trips is handed to a second kernel in which a whole wave
                         finishes it (same results; keeps one far-off query from

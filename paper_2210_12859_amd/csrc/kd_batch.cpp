@@ -139,7 +139,7 @@ kd_status kd_batch_create(const kd_job* jobs, int n_jobs, const kd_opts* opts, k
                          hipMemcpyHostToDevice));
         const size_t sort_b = (batch_sort_scratch_bytes(c.n) + 255) & ~size_t(255);
         const size_t rec_b = (size_t(c.n) * batch_rec_bytes() + 255) & ~size_t(255);
-        KD_HIP(hipMalloc(&b->classes.back().ws, sort_b + rec_b + 32 * 1024));
+        KD_HIP(hipMalloc(&b->classes.back().ws, sort_b + rec_b + batch_cursor_bytes()));
     }
 
     // capture the whole batch as one graph (on a private stream when the

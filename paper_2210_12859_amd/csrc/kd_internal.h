@@ -161,6 +161,7 @@ kd_status batch_sort(const BatchJob* d_jobs, int njobs, int dim, uint32_t n, int
 kd_status run_batch_class(const BatchJob* d_jobs, int njobs, int dim, int K, uint32_t n, const uint32_t* perm,
                           void* recs, uint32_t* counters, const QueryPlan& plan, int device, hipStream_t st);
 size_t batch_rec_bytes();
+size_t batch_cursor_bytes();  // work cursors of one class launch
 // Morton reorder of query slots (kd_sort.hip)
 size_t sort_scratch_bytes(int64_t Q, int dim);
 // Writes the queries as traversal records (NodeRec<dim>[Q]) into sq, in

@@ -397,30 +397,48 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
 // traverse the same region of the tree and share its L1 working set.
 // Workgroups on one XCD (blockIdx % 8) get neighbouring ranges, so the XCD's
 // L2 holds one region too.  A wave takes chunks of its group's range until it
-// is used up -- chunks shrink as the range drains -- then steals from up to
-// STEAL_PROBES following ranges.  Stealing is only a speed-up: every range is
-// drained by its own group's waves, so no slot is ever left behind.
-constexpr uint32_t STEAL_PROBES = 32;
+// is used up -- chunks shrink as the range drains -- then steals: one lane per
+// range reads the cursors of the STEAL_PROBES following ranges (plain atomic
+// loads, no read-modify-write), the wave takes the range with the most slots
+// left and claims chunks from it until it is used up, then looks again.
+// Only a range with at least STEAL_MIN slots left is a victim: near the end of
+// a balanced batch, moving queries away from the caches that hold their region
+// costs more than the idle waves (measured).  Stealing is only a speed-up:
+// every range is drained by its own group's waves, so no slot is ever left
+// behind.  Cursors sit CURSOR_STRIDE words
+// apart so that different ranges' atomics do not share a line.
+#ifndef KD_STEAL_PROBES
+#define KD_STEAL_PROBES 16
+#endif
+constexpr uint32_t STEAL_PROBES = KD_STEAL_PROBES;  // at most 64 (one per lane)
+#ifndef KD_STEAL_MIN
+#define KD_STEAL_MIN 64
+#endif
+constexpr uint32_t STEAL_MIN = KD_STEAL_MIN;           // slots a victim must have left
+constexpr uint32_t CURSOR_STRIDE = 8;
+constexpr uint32_t MAX_GROUPS = 8192;                // persistent workgroups per launch
 
 struct WorkSource {
     uint32_t r0;        // own range
     uint32_t G;         // number of ranges (= workgroups)
-    uint32_t src;       // ranges tried so far
+    uint32_t src;       // range claimed from: r0 first, then a victim
     uint32_t want;      // next chunk size, 1..64
     uint32_t wpg;       // waves per workgroup
     bool exhausted;
 
+    __device__ __forceinline__ uint32_t begin_of(const TravArgs& a, uint32_t r) const {
+        return uint32_t((uint64_t(r) * a.Q) / G);
+    }
+
     __device__ __forceinline__ void grab(const TravArgs& a, uint32_t lane, uint32_t& cb, uint32_t& cn) {
         cb = 0;
         cn = 0;
-        const uint32_t limit = G < STEAL_PROBES + 1 ? G : STEAL_PROBES + 1;
-        while (src < limit) {
-            uint32_t r = r0 + src;
-            if (r >= G) r -= G;
-            const uint32_t beg = uint32_t((uint64_t(r) * a.Q) / G);
-            const uint32_t end = uint32_t((uint64_t(r + 1) * a.Q) / G);
+        while (!exhausted) {
+            const uint32_t r = src;
+            const uint32_t beg = begin_of(a, r);
+            const uint32_t end = begin_of(a, r + 1);
             uint32_t c = 0;
-            if (lane == 0) c = atomicAdd(&a.counter[r], want);
+            if (lane == 0) c = atomicAdd(&a.counter[r * CURSOR_STRIDE], want);
             c = __builtin_amdgcn_readfirstlane(c);
             if (c < end - beg) {
                 cb = beg + c;
@@ -430,10 +448,33 @@ struct WorkSource {
                 want = w < 1 ? 1 : (w > 64 ? 64 : w);
                 return;
             }
-            ++src;
-            want = 16;
+            // this range is used up: pick the fullest of the following ranges
+            const uint32_t probes = G - 1 < STEAL_PROBES ? G - 1 : STEAL_PROBES;
+            uint32_t rr = r0 + 1 + lane;
+            rr = rr >= G ? rr - G : rr;
+            uint32_t left = 0;
+            if (lane < probes) {
+                const uint32_t size = begin_of(a, rr + 1) - begin_of(a, rr);
+                const uint32_t cur =
+                    __hip_atomic_load(&a.counter[rr * CURSOR_STRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                left = cur < size ? size - cur : 0;
+            }
+            // only ranges with a good amount of work left are worth moving
+            // queries away from the L1 / L2 that holds their region
+            if (!wave_any(left >= STEAL_MIN)) {
+                exhausted = true;
+                return;
+            }
+            uint32_t best = left;
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) {
+                const uint32_t o = __shfl_xor(best, m);
+                best = o > best ? o : best;
+            }
+            src = __builtin_amdgcn_readlane(rr, int(__builtin_ctzll(wave_ballot(left == best))));
+            const uint32_t w = best / (2 * wpg);
+            want = w < 1 ? 1 : (w > 64 ? 64 : w);
         }
-        exhausted = true;
     }
 };
 
@@ -444,16 +485,23 @@ __device__ __forceinline__ uint32_t group_range(uint32_t g, uint32_t G) {
 }
 
 constexpr int max_block(int K) { return K >= 32 ? 256 : 1024; }
+// minimum waves per SIMD the register allocation must allow: the 64-entry
+// list (128 VGPRs) would otherwise leave room for only two
+#ifndef KD_MIN_WAVES_K64
+#define KD_MIN_WAVES_K64 3
+#endif
+constexpr int min_waves(int K) { return K >= 64 ? KD_MIN_WAVES_K64 : 1; }
 
 template <int D, int K, int F, bool LEARNED>
-__global__ __launch_bounds__(max_block(K)) void knn_persistent(TravArgs a) {
+__global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(TravArgs a) {
     const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);  // indexed by node id
     const int32_t* __restrict__ ids = node_ids<D>(g1, a.N);
     const NodeRec<D>* __restrict__ sq = reinterpret_cast<const NodeRec<D>*>(a.sq);
 
     const uint32_t lane = __lane_id();
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
-    WorkSource ws{group_range(blockIdx.x, gridDim.x), gridDim.x, 0u, 64u, blockDim.x >> 6, false};
+    const uint32_t own = group_range(blockIdx.x, gridDim.x);
+    WorkSource ws{own, gridDim.x, own, 64u, blockDim.x >> 6, false};
     // Query chunk held across the wave: lane l holds slot cb + l of the
     // current chunk (record and, when learned, initial radius); idle lanes
     // take queries from it by cross-lane shuffle.
@@ -954,7 +1002,8 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
     TravArgs wa = {};
     wa.Q = a.Q;
     wa.counter = a.counter;
-    WorkSource ws{group_range(blockIdx.x, gridDim.x), gridDim.x, 0u, 64u, blockDim.x >> 6, false};
+    const uint32_t own = group_range(blockIdx.x, gridDim.x);
+    WorkSource ws{own, gridDim.x, own, 64u, blockDim.x >> 6, false};
     BRec chunk;
     uint32_t cpos = 0, cn = 0;
     Lane<D, K> s;
@@ -1066,6 +1115,7 @@ hipError_t launch_radius_to_worst0(int D, const float* r0, const void* sq, uint3
 }  // namespace
 
 size_t batch_rec_bytes() { return sizeof(BRec); }
+size_t batch_cursor_bytes() { return size_t(MAX_GROUPS) * CURSOR_STRIDE * 4; }
 
 // One (dim, K) class of a batched call: gather into class records, zero the
 // range cursors, one persistent traversal launch.
@@ -1092,9 +1142,11 @@ kd_status run_batch_class(const BatchJob* d_jobs, int njobs, int dim, int K, uin
     int64_t grid = int64_t(dev.cus) * per_cu;
     const int64_t need = (int64_t(n) + block - 1) / block;
     if (grid > need) grid = need;
+    if (grid > MAX_GROUPS) grid = MAX_GROUPS;
     if (grid > 8 && grid % 8) grid -= grid % 8;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(zero_u32, dim3(unsigned((grid + 255) / 256)), dim3(256), 0, st, counters, int(grid));
+    const int ncur = int(grid) * int(CURSOR_STRIDE);
+    hipLaunchKernelGGL(zero_u32, dim3(unsigned((ncur + 255) / 256)), dim3(256), 0, st, counters, ncur);
     KD_HIP(hipGetLastError());
     BatchArgs a{d_jobs, reinterpret_cast<const BRec*>(recs), n, counters};
     e = dim == 2 ? dispatch_batched_k<2>(K, a, block, int(grid), st)
@@ -1120,7 +1172,8 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     // The per-query visited count is the single-lane traversal's, so there
     // is no hand-off when it is requested.
     const bool handoff = plan.heavy_trips > 0 && visited == nullptr;
-    const size_t head = 72 * 1024;
+    const size_t cursor_bytes = size_t(MAX_GROUPS) * CURSOR_STRIDE * 4;  // 256 KB
+    const size_t head = cursor_bytes + 4096;
     const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
     const size_t sort_bytes = plan.sort_bits > 0 ? sort_scratch_bytes(Q, t->dim) : 0;
     const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
@@ -1130,14 +1183,14 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     if (s != KD_OK) return s;
     char* base = static_cast<char*>(ws);
     uint32_t* counter1 = reinterpret_cast<uint32_t*>(base);
-    uint32_t* fb_count = reinterpret_cast<uint32_t*>(base + 64 * 1024);
-    uint32_t* heavy_count = reinterpret_cast<uint32_t*>(base + 64 * 1024 + 4);
+    uint32_t* fb_count = reinterpret_cast<uint32_t*>(base + cursor_bytes);
+    uint32_t* heavy_count = reinterpret_cast<uint32_t*>(base + cursor_bytes + 4);
     void* sq = base + head;
     void* sort_ws = base + head + sq_bytes;
     float* worst0 = learned ? reinterpret_cast<float*>(base + head + sq_bytes + sort_bytes) : nullptr;
     int32_t* heavy_rows = handoff ? reinterpret_cast<int32_t*>(base + head + sq_bytes + sort_bytes + learn_bytes)
                                   : nullptr;
-    const uint32_t n_counters = 16 * 1024 + 2;  // range cursors, restart count, hand-off count
+    const uint32_t n_counters = uint32_t(cursor_bytes / 4) + 2;  // range cursors, restart count, hand-off count
 
     // query reorder: Morton sort whose last pass writes the traversal records
     hipEvent_t evs;
@@ -1202,6 +1255,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     int64_t grid = int64_t(dev.cus) * per_cu;
     const int64_t need = (Q + block - 1) / block;
     if (grid > need) grid = need;
+    if (grid > MAX_GROUPS) grid = MAX_GROUPS;
     if (grid > 8 && grid % 8) grid -= grid % 8;
     if (grid < 1) grid = 1;
     hipEvent_t ev0;
