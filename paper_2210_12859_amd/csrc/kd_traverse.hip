@@ -399,8 +399,9 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
 // L2 holds one region too.  A wave takes chunks of its group's range until it
 // is used up -- chunks shrink as the range drains -- then steals: one lane per
 // range reads the cursors of the STEAL_PROBES following ranges (plain atomic
-// loads, no read-modify-write), the wave takes the range with the most slots
-// left and claims chunks from it until it is used up, then looks again.
+// loads, no read-modify-write), the wave takes the nearest one with enough
+// slots left (batched launches: the fullest one) and claims chunks from it
+// until it is used up, then looks again.
 // Only a range with at least STEAL_MIN slots left is a victim: near the end of
 // a balanced batch, moving queries away from the caches that hold their region
 // costs more than the idle waves (measured).  Stealing is only a speed-up:
@@ -414,7 +415,7 @@ constexpr uint32_t STEAL_PROBES = KD_STEAL_PROBES;  // at most 64 (one per lane)
 #ifndef KD_STEAL_MIN
 #define KD_STEAL_MIN 64
 #endif
-constexpr uint32_t STEAL_MIN = KD_STEAL_MIN;           // slots a victim must have left
+constexpr uint32_t STEAL_MIN = KD_STEAL_MIN;           // single-tree launches: slots a victim must have left
 constexpr uint32_t CURSOR_STRIDE = 8;
 constexpr uint32_t MAX_GROUPS = 8192;                // persistent workgroups per launch
 
@@ -425,11 +426,24 @@ struct WorkSource {
     uint32_t want;      // next chunk size, 1..64
     uint32_t wpg;       // waves per workgroup
     bool exhausted;
+    uint32_t base, extra;  // range r holds base + (r < extra) slots
+    uint32_t steal_min;    // slots a victim must have left
 
-    __device__ __forceinline__ uint32_t begin_of(const TravArgs& a, uint32_t r) const {
-        return uint32_t((uint64_t(r) * a.Q) / G);
+    __device__ __forceinline__ WorkSource(uint32_t own, uint32_t groups, uint32_t waves_per_group, uint32_t Q,
+                                          uint32_t min_left)
+        : r0(own), G(groups), src(own), want(64u), wpg(waves_per_group), exhausted(false), steal_min(min_left) {
+        base = Q / G;
+        extra = Q - base * G;
     }
 
+    __device__ __forceinline__ uint32_t begin_of(const TravArgs& a, uint32_t r) const {
+        (void)a;
+        return r * base + (r < extra ? r : extra);
+    }
+
+    // FULLEST: victim = the range with most slots left (stealers spread out;
+    // costs registers), else the nearest one with at least steal_min left.
+    template <bool FULLEST>
     __device__ __forceinline__ void grab(const TravArgs& a, uint32_t lane, uint32_t& cb, uint32_t& cn) {
         cb = 0;
         cn = 0;
@@ -461,17 +475,25 @@ struct WorkSource {
             }
             // only ranges with a good amount of work left are worth moving
             // queries away from the L1 / L2 that holds their region
-            if (!wave_any(left >= STEAL_MIN)) {
+            const uint64_t rich = wave_ballot(left >= steal_min);
+            if (!rich) {
                 exhausted = true;
                 return;
             }
-            uint32_t best = left;
+            uint32_t best;
+            if constexpr (FULLEST) {
+                best = left;
 #pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) {
-                const uint32_t o = __shfl_xor(best, m);
-                best = o > best ? o : best;
+                for (int m = 32; m >= 1; m >>= 1) {
+                    const uint32_t o = __shfl_xor(best, m);
+                    best = o > best ? o : best;
+                }
+                src = __builtin_amdgcn_readlane(rr, int(__builtin_ctzll(wave_ballot(left == best))));
+            } else {
+                const int at = int(__builtin_ctzll(rich));
+                src = __builtin_amdgcn_readlane(rr, at);
+                best = __builtin_amdgcn_readlane(left, at);
             }
-            src = __builtin_amdgcn_readlane(rr, int(__builtin_ctzll(wave_ballot(left == best))));
             const uint32_t w = best / (2 * wpg);
             want = w < 1 ? 1 : (w > 64 ? 64 : w);
         }
@@ -500,8 +522,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
 
     const uint32_t lane = __lane_id();
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
-    const uint32_t own = group_range(blockIdx.x, gridDim.x);
-    WorkSource ws{own, gridDim.x, own, 64u, blockDim.x >> 6, false};
+    WorkSource ws(group_range(blockIdx.x, gridDim.x), gridDim.x, blockDim.x >> 6, a.Q, STEAL_MIN);
     // Query chunk held across the wave: lane l holds slot cb + l of the
     // current chunk (record and, when learned, initial radius); idle lanes
     // take queries from it by cross-lane shuffle.
@@ -531,7 +552,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
             cpos += take1;
             if (n > take1) {
                 uint32_t cb = 0, cn2 = 0;
-                ws.grab(a, lane, cb, cn2);
+                ws.grab<false>(a, lane, cb, cn2);
                 if (cn2) {
                     if (lane < cn2) {
                         chunk = load_query<D>(sq + cb + lane);
@@ -1002,8 +1023,9 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
     TravArgs wa = {};
     wa.Q = a.Q;
     wa.counter = a.counter;
-    const uint32_t own = group_range(blockIdx.x, gridDim.x);
-    WorkSource ws{own, gridDim.x, own, 64u, blockDim.x >> 6, false};
+    // the classes of a batch mix trees and k, so their ranges drain unevenly:
+    // any slot left is worth stealing
+    WorkSource ws(group_range(blockIdx.x, gridDim.x), gridDim.x, blockDim.x >> 6, a.Q, 1u);
     BRec chunk;
     uint32_t cpos = 0, cn = 0;
     Lane<D, K> s;
@@ -1024,7 +1046,7 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
             cpos += take1;
             if (n > take1) {
                 uint32_t cb = 0, cn2 = 0;
-                ws.grab(wa, lane, cb, cn2);
+                ws.grab<true>(wa, lane, cb, cn2);
                 if (cn2) {
                     if (lane < cn2) chunk = load_brec(a.recs + cb + lane);
                     cn = cn2;
