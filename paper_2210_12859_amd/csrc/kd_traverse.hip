@@ -22,9 +22,9 @@
 // Several state-machine steps run per loop trip, always in the paper's order:
 //   * a step onto a child that does not exist (id > N) and the bounce back
 //     are resolved in place: the next node is the one the bounce would pick;
-//   * "return to parent" steps are resolved with the ancestor split values
-//     stored in the current node's record (up to three levels), so a lane
-//     does not reload its parents to learn which child it came from.
+//   * a "return to parent" step is resolved with the parent's split value
+//     stored in the current node's record (KD_FUSED_LEVELS = 1 level), so a
+//     lane does not reload its parent to learn which child it came from.
 // The processed-node sequence therefore equals the paper's, and the ordered
 // recursion's, node for node.
 //
