@@ -9,9 +9,13 @@ line.  The roofline figure is for the traversal kernel: algorithmic bytes =
 processed nodes x dim x 4 B (node data touched), divided by the kernel's mean
 duration from hipEvents recorded around each launch on its own stream.
 
-The same line carries the learned-radius variant on the same queries
-("learned"), a batched many-tree measurement ("batched") and the CPU oracle
-timed on the host ("cpu_baseline"); each can be skipped by a flag.
+The headline ("plain") is the paper's traversal: the far child is pruned by
+its split plane only (kd_opts.prune = 1).  The same line carries the
+library's default rule, which also leaves a subtree on entry when its
+bounding box is out of range ("boxes", identical results, fewer nodes), the
+learned-radius variant on the same queries ("learned", paper's rule), a
+batched many-tree measurement ("batched") and the CPU oracle timed on the
+host ("cpu_baseline"); each can be skipped by a flag.
 """
 from __future__ import annotations
 
@@ -28,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "kNN queries/sec (k=8, 1M pts) plain vs learned-radius; % HBM peak"
 HBM_PEAK_GBPS = 8000.0
+PLAIN = {"prune": 1}  # the paper's split-plane pruning rule
 
 WORKLOADS = {
     "uniform-1m": "N=1,048,576 uniform float32 3-D points in [0,1)^3 (seed 0); Q=1,048,576 uniform queries (seed 1)",
@@ -91,6 +96,43 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_calibration_bytes": nbytes, "launches": reps}), flush=True)
 
 
+def bench_boxes(kd, tree, q, oi, od, k, args, plain_ms):
+    """The library's default pruning rule on the same queries (kd_knn with no
+    options): split planes plus subtree bounding boxes.  Timed like the plain
+    step; results checked identical to the plain results."""
+    import torch
+    dev = q.device
+    bi = torch.empty_like(oi)
+    bd = torch.empty_like(od)
+    kd.kd_knn(tree, q, k, out_idx=bi, out_d2=bd)
+    _, _, vis = kd.kd_knn_ex(tree, q, k, want_visited=True, opts={"prune": 2})
+    torch.cuda.synchronize()
+    identical = bool(torch.equal(bi, oi) and torch.equal(bd.view(torch.int32), od.view(torch.int32)))
+    entered = int(vis.to(torch.int64).sum().item())
+    for _ in range(args.warmup):
+        kd.kd_knn(tree, q, k, out_idx=bi, out_d2=bd)
+    torch.cuda.synchronize()
+    kd.kd_timing_enable(True)
+    kd.kd_timing_collect("traverse")
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        kd.kd_knn(tree, q, k, out_idx=bi, out_d2=bd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    tot, n = kd.kd_timing_collect("traverse")
+    kd.kd_timing_enable(False)
+    value = q.shape[0] / (ms / 1e3)
+    log(f"boxes: {ms:.3f} ms/step, {value / 1e6:.1f} M queries/s ({plain_ms / ms:.3f}x plain), "
+        f"entered {entered / q.shape[0]:.1f}/query, identical {identical}")
+    return {"value": value, "unit": "queries/s", "ms_per_step": ms, "traverse_ms": tot / max(1, n),
+            "speedup_vs_plain": plain_ms / ms, "identical_to_plain": identical,
+            "entered_per_query": entered / q.shape[0]}
+
+
 def bench_learned(kd, datagen, tree, q, oi, od, k, args, plain_visited, plain_ms):
     """Learned initial radius on the same queries: train (untimed) on separate
     queries of the same distribution, then time kd_knn_learned like the plain
@@ -107,12 +149,13 @@ def bench_learned(kd, datagen, tree, q, oi, od, k, args, plain_visited, plain_ms
     li = torch.empty_like(oi)
     ld = torch.empty_like(od)
     vis = torch.empty(q.shape[0], dtype=torch.int32, device=dev)
-    _, _, _, st = kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld, visited=vis, want_stats=True)
+    _, _, _, st = kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld, visited=vis, want_stats=True,
+                                    opts=PLAIN)
     torch.cuda.synchronize()
     identical = bool(torch.equal(li, oi) and torch.equal(ld.view(torch.int32), od.view(torch.int32)))
     lvis = int(vis.to(torch.int64).sum().item())
     for _ in range(args.warmup):
-        kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld)
+        kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld, opts=PLAIN)
     torch.cuda.synchronize()
     kd.kd_timing_enable(True)
     for name in ("sort", "mlp", "traverse", "fallback"):
@@ -122,7 +165,7 @@ def bench_learned(kd, datagen, tree, q, oi, od, k, args, plain_visited, plain_ms
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(args.steps):
-        kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld)
+        kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld, opts=PLAIN)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
@@ -209,6 +252,7 @@ def main():
     ap.add_argument("--k", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-radius variant")
+    ap.add_argument("--no-boxes", action="store_true", help="skip the default (bounding-box) pruning variant")
     ap.add_argument("--train-epochs", type=int, default=8)
     ap.add_argument("--batch-jobs", type=int, default=128, help="trees in the batched measurement (0 = skip)")
     ap.add_argument("--batch-nmax", type=int, default=262144, help="largest tree of the batched measurement")
@@ -252,7 +296,7 @@ def main():
     log(f"mean processed nodes/query = {visited_total / Q:.2f}")
 
     for _ in range(args.warmup):
-        kd.kd_knn(tree, q, k, out_idx=oi, out_d2=od)
+        kd.kd_knn_ex(tree, q, k, out_idx=oi, out_d2=od, opts=PLAIN)
     torch.cuda.synchronize()
     kd.kd_timing_enable(True)
     kd.kd_timing_collect("traverse")
@@ -262,7 +306,7 @@ def main():
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
-        kd.kd_knn(tree, q, k, out_idx=oi, out_d2=od)
+        kd.kd_knn_ex(tree, q, k, out_idx=oi, out_d2=od, opts=PLAIN)
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
@@ -301,6 +345,8 @@ def main():
         "visited_per_query": visited_total / Q,
         "nodes_visited_per_s": visited_total / (ms_per_step / 1e3),
     }
+    if not args.no_boxes:
+        out["boxes"] = bench_boxes(kd, tree, q, oi, od, k, args, ms_per_step)
     if not args.no_learned and D == 3:
         out["learned"] = bench_learned(kd, datagen, tree, q, oi, od, k, args, visited_total, ms_per_step)
     if args.batch_jobs > 0:

@@ -78,6 +78,16 @@ typedef struct {
                         (KD_DEFAULT_HEAVY_TRIPS).  No hand-off happens when the
                         per-query visited count is requested, which is the
                         single-lane traversal's by definition. */
+    int prune;       /* pruning rule (results are identical under both):
+                        1 = split planes only, the paper's rule (the far child
+                        is entered when the squared distance to its split
+                        plane is <= the current k-th distance);
+                        2 = that, and a subtree whose bounding box (of its
+                        points, stored with the tree) lies farther than the
+                        k-th distance is left on entry without processing any
+                        of its nodes;
+                        0 = default: 2, or 1 when the visited count is
+                        requested. */
 } kd_opts;
 
 #define KD_DEFAULT_HEAVY_TRIPS 1024
@@ -131,8 +141,11 @@ kd_status kd_fcp(kd_tree t, const float* queries, int64_t Q, float maxRadius,
 kd_status kd_knn(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius,
                  int32_t* out_idx, float* out_d2, kd_stream stream);
 
-/* kd_knn with launch options and an optional per-query count of processed
- * nodes (first visits of existing nodes; the paper's processNode calls):
+/* kd_knn with launch options and an optional per-query count of entered
+ * nodes (first visits of existing nodes).  Under the paper's pruning rule
+ * (opts.prune 1, the default when visited is given) every entered node is
+ * processed, so this is the paper's processNode count; under prune = 2 it
+ * also counts subtrees left at their root by the bounding-box test.
  *   visited : device uint32 [Q] or NULL.   opts : may be NULL. */
 kd_status kd_knn_ex(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius,
                     int32_t* out_idx, float* out_d2, uint32_t* visited,

@@ -48,7 +48,8 @@ class KdJob(ctypes.Structure):
 
 class KdOpts(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("lds_levels", ctypes.c_int),
-                ("sort_bits", ctypes.c_int), ("waves_per_cu", ctypes.c_int), ("heavy_trips", ctypes.c_int)]
+                ("sort_bits", ctypes.c_int), ("waves_per_cu", ctypes.c_int), ("heavy_trips", ctypes.c_int),
+                ("prune", ctypes.c_int)]
 
 
 def lib():
@@ -222,7 +223,7 @@ def _opts(opts):
     if isinstance(opts, KdOpts):
         return ctypes.byref(opts)
     o = KdOpts(opts.get("block", 0), opts.get("lds_levels", -1), opts.get("sort_bits", -1),
-               opts.get("waves_per_cu", 0), opts.get("heavy_trips", 0))
+               opts.get("waves_per_cu", 0), opts.get("heavy_trips", 0), opts.get("prune", 0))
     return ctypes.byref(o)
 
 
@@ -444,7 +445,7 @@ def kd_knn_batched(jobs, opts=None, stream=None):
 
 def _opts_dict(o: KdOpts):
     return dict(block=o.block, lds_levels=o.lds_levels, sort_bits=o.sort_bits, waves_per_cu=o.waves_per_cu,
-                heavy_trips=o.heavy_trips)
+                heavy_trips=o.heavy_trips, prune=o.prune)
 
 
 def kd_autotune(tree: Tree, sample_q, k, max_radius=math.inf, stream=None):
@@ -466,7 +467,7 @@ def kd_tree_get_tuned(tree: Tree, k):
 
 def kd_tree_set_tuned(tree: Tree, k, opts: dict):
     o = KdOpts(opts.get("block", 0), opts.get("lds_levels", -1), opts.get("sort_bits", -1),
-               opts.get("waves_per_cu", 0), opts.get("heavy_trips", 0))
+               opts.get("waves_per_cu", 0), opts.get("heavy_trips", 0), opts.get("prune", 0))
     _check(lib().kd_tree_set_tuned(tree.handle, int(k), ctypes.byref(o)))
 
 

@@ -2,6 +2,7 @@
 // tree objects, per-stream scratch, and dispatch into the HIP pipeline.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -135,6 +136,25 @@ void pack_records(const float* pts, const int32_t* order, int64_t N, std::vector
     }
 }
 
+// Bounding box of the points of every subtree, children before parents:
+// node id i (1-based) covers its own point and the boxes of ids 2i, 2i + 1.
+void pack_boxes(const float* pts, const int32_t* order, int64_t N, int D, std::vector<float>& out) {
+    const int BW = box_words(D), H = BW / 2;
+    out.assign(size_t(N + 2) * BW, 0.0f);
+    for (int64_t id = N; id >= 1; --id) {
+        float* b = &out[size_t(id) * BW];
+        const float* p = &pts[int64_t(order[id - 1]) * D];
+        for (int j = 0; j < D; ++j) b[j] = b[H + j] = p[j];
+        for (int64_t c = 2 * id; c <= 2 * id + 1 && c <= N; ++c) {
+            const float* cb = &out[size_t(c) * BW];
+            for (int j = 0; j < D; ++j) {
+                b[j] = std::min(b[j], cb[j]);
+                b[H + j] = std::max(b[H + j], cb[H + j]);
+            }
+        }
+    }
+}
+
 kd_status build_from_host(const float* hp, int64_t N, int dim, kd_tree* out) {
     if (!out) return set_error(KD_EINVAL, "kd_build: out is NULL");
     if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build: N out of range [0, 2^30]");
@@ -174,6 +194,21 @@ kd_status build_from_host(const float* hp, int64_t N, int dim, kd_tree* out) {
             (void)hipFree(t->d_nodes);
             return hip_error(e, "kd_build: upload");
         }
+        std::vector<unsigned char>().swap(recs);
+        std::vector<float> boxes;
+        try {
+            pack_boxes(hp, t->order.data(), N, dim, boxes);
+        } catch (...) {
+            (void)hipFree(t->d_nodes);
+            return set_error(KD_ENOMEM, "kd_build: host allocation");
+        }
+        e = hipMalloc(&t->d_boxes, boxes.size() * 4);
+        if (e == hipSuccess) e = hipMemcpy(t->d_boxes, boxes.data(), boxes.size() * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(t->d_nodes);
+            if (t->d_boxes) (void)hipFree(t->d_boxes);
+            return hip_error(e, "kd_build: upload");
+        }
     }
     *out = t.release();
     return KD_OK;
@@ -209,10 +244,15 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     p.K = k_template(k);
     float r = maxRadius;
     p.R2 = r * r;  // binary32 product; +inf stays +inf
-    kd_opts use{0, -1, -1, 0, 0};
+    kd_opts use{0, -1, -1, 0, 0, 0};
     kd_opts tuned;
     if (o) use = *o;
-    else if (t && tuned_opts(t, p.K, &tuned)) use = tuned;
+    else if (t && tuned_opts(t, p.K, &tuned)) {
+        use = tuned;
+        // a tuned box rule is the default rule, which still gives the
+        // paper's count when visited is requested
+        if (use.prune == 2) use.prune = 0;
+    }
     if (use.block == 0) use.block = 256;
     if (use.lds_levels < 0) use.lds_levels = 0;
     if (use.sort_bits < 0) use.sort_bits = 16;
@@ -225,11 +265,13 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     if (use.sort_bits > 32) return set_error(KD_EINVAL, "opts.sort_bits must be in 0..32 or -1");
     use.sort_bits = ((use.sort_bits + 7) / 8) * 8;  // the radix sort takes whole bytes
     if (use.waves_per_cu < 1 || use.waves_per_cu > 32) return set_error(KD_EINVAL, "opts.waves_per_cu must be in 1..32");
+    if (use.prune < 0 || use.prune > 2) return set_error(KD_EINVAL, "opts.prune must be 0, 1 or 2");
     p.block = use.block;
     p.lds_levels = use.lds_levels;
     p.sort_bits = use.sort_bits;
     p.waves_per_cu = use.waves_per_cu;
     p.heavy_trips = use.heavy_trips > 0 ? use.heavy_trips : 0;
+    p.prune = use.prune;
     return KD_OK;
 }
 
@@ -313,6 +355,7 @@ kd_status kd_build_order_host(const float* host_points, int64_t N, int dim, int3
 kd_status kd_tree_free(kd_tree t) {
     if (!t) return KD_OK;
     if (t->d_nodes) (void)hipFree(t->d_nodes);
+    if (t->d_boxes) (void)hipFree(t->d_boxes);
     delete t;
     return KD_OK;
 }

@@ -54,6 +54,13 @@ struct alignas(4 * rec_words(D)) TreeRec {
     uint32_t w[rec_words(D)];
 };
 
+// Subtree bounding boxes, one per node id: the per-dimension minimum of the
+// points of the node's subtree at words 0..D-1, the maximum at words
+// box_words(D)/2 .. box_words(D)/2 + D-1 (D = 3 pads both halves to 4 words,
+// so a box is two aligned dwordx4 loads).
+constexpr int box_words(int D) { return D == 2 ? 4 : 8; }
+inline size_t box_buffer_bytes(int D, int64_t N) { return size_t(N + 2) * 4 * size_t(box_words(D)); }
+
 // Tuned launch parameters kept with a tree (filled by kd_autotune).
 struct TuneEntry {
     int k_template;  // compiled list size
@@ -72,6 +79,8 @@ struct kd_tree_s {
     float hi[4] = {0, 0, 0, 0};
     void* d_nodes = nullptr;       // node buffer: TreeRec<dim>[N + 2], record of node id i at index i
                                    // (+ int32 index[N + 2] when the record holds no index)
+    void* d_boxes = nullptr;       // float[N + 2][box_words(dim)]: bounding box of the points of the
+                                   // subtree of node id i (lows, then highs) at index i
     std::vector<int32_t> order;    // host copy: order[pos] = caller index
     std::mutex tune_mu;
     std::vector<kd::TuneEntry> tuned;
@@ -126,6 +135,7 @@ struct QueryPlan {
     int sort_bits = 32;
     int waves_per_cu = 8;
     int heavy_trips = 0;  // trip budget before the cooperative hand-off, 0 = none
+    int prune = 0;        // kd_opts.prune: 0 default, 1 split planes, 2 subtree boxes
 };
 int k_template(int k);
 

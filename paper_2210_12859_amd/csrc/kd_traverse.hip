@@ -59,6 +59,8 @@ constexpr uint32_t SENT_IDX = 0x7fffffffu;
 
 struct TravArgs {
     const void* nodes;       // TreeRec<D>[N + 2], record of node id i at index i
+    const float* boxes;      // [N + 2][box_words(D)] subtree bounding boxes (BOX kernels)
+    int32_t box_below;       // boxes are tested for node ids below this (subtrees tall enough)
     int32_t N;
     const void* sq;          // NodeRec<D>[Q]: queries in traversal order, .idx = caller row
     uint32_t Q;              // query slots
@@ -175,6 +177,37 @@ __device__ __forceinline__ void load_tree_uniform(const TreeRec<D>* g1, int32_t 
     idx = rec_has_idx(D) ? int32_t(w[D]) : 0;
 }
 
+// Lower bound of the squared distance from q to every point of the subtree
+// of node id `id`, from the subtree's bounding box.  Per dimension the offset
+// is q - low below the box, q - high above it, else 0; the squares are summed
+// in the order of the point distance, without contraction.  Rounding is
+// monotonic, so for each point p of the box |fl(q - p)| >= |offset| per
+// dimension and the point's d2 is >= this sum: a subtree whose bound exceeds
+// the current k-th distance holds no point of the result.
+template <int D>
+__device__ __forceinline__ float box_d2(const float* __restrict__ boxes, int32_t id, const float (&q)[D]) {
+    constexpr int H = box_words(D) / 2;
+    const uint4* p = reinterpret_cast<const uint4*>(boxes + int64_t(id) * box_words(D));
+    float w[8];
+    const uint4 a = p[0];
+    w[0] = __uint_as_float(a.x); w[1] = __uint_as_float(a.y); w[2] = __uint_as_float(a.z); w[3] = __uint_as_float(a.w);
+    if (box_words(D) == 8) {
+        const uint4 b = p[1];
+        w[4] = __uint_as_float(b.x); w[5] = __uint_as_float(b.y); w[6] = __uint_as_float(b.z); w[7] = __uint_as_float(b.w);
+    }
+    float o[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const float below = q[j] - w[j];      // < 0 when q is below the box
+        const float above = q[j] - w[H + j];  // > 0 when q is above it
+        o[j] = below < 0.0f ? below : (above > 0.0f ? above : 0.0f);
+    }
+    float d2 = o[0] * o[0];
+#pragma unroll
+    for (int j = 1; j < D; ++j) d2 = d2 + o[j] * o[j];
+    return d2;
+}
+
 // Caller-index array of a node buffer whose records hold no index.
 template <int D>
 __device__ __forceinline__ const int32_t* node_ids(const TreeRec<D>* g1, int32_t N) {
@@ -231,6 +264,7 @@ struct Lane {
     uint32_t trips;    // loop trips spent on the current query
     float w0;          // initial squared radius of the current run
     bool fell_back;    // the learned run found < k points and was restarted
+    bool far_entry;    // the last step moved into a far child
 };
 
 template <int D, int K>
@@ -243,6 +277,7 @@ __device__ __forceinline__ void lane_reset(Lane<D, K>& s, int k, float w0) {
     for (int j = 0; j < K; ++j) s.L[j] = (j < K - k) ? uint64_t(0) : sent;
     s.curr = 1;   // root
     s.prev = 0;   // the root's parent
+    s.far_entry = false;
 }
 
 template <int D, int K, bool LEARNED>
@@ -310,7 +345,8 @@ template <int D, int K, int F, bool CAP = false>
 __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D], int32_t idx,
                                              const int32_t* __restrict__ ids,
                                              const float (&anc)[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1],
-                                             int32_t N, float cap = 0.0f, int32_t stop = 0) {
+                                             int32_t N, float cap = 0.0f, int32_t stop = 0,
+                                             bool skip = false) {
     const int32_t curr = s.curr;
     const DimSel<D> dim(curr);
     float dx[D];
@@ -318,10 +354,13 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     for (int j = 0; j < D; ++j) dx[j] = s.q[j] - c[j];
     const float sd = dim.template rot<0>(dx);
     const bool from_parent = s.prev < curr;
-    if (from_parent) {
+    // skip: the caller found the subtree out of range on entry; it is left
+    // at once, as if coming back from it
+    const bool enter = from_parent & !skip;
+    if (from_parent) ++s.vis;  // entered nodes
+    if (enter) {
         // processNode on the first visit: exact binary32 squared distance,
         // left to right, and insertion into the k-best list
-        ++s.vis;
         float d2 = dx[0] * dx[0];
 #pragma unroll
         for (int j = 1; j < D; ++j) d2 = d2 + dx[j] * dx[j];
@@ -344,13 +383,14 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     const int32_t close_c = (curr << 1) | (sd > 0.0f ? 1 : 0);
     const int32_t far_c = close_c ^ 1;
     const bool close_missing = close_c > N;
-    const bool go_close = from_parent & !close_missing;
+    const bool go_close = enter & !close_missing;
     // the far child is tried when coming from the parent with no close
     // child, or when coming back from the close child (prev == close_c
     // implies prev > curr, i.e. not from the parent)
-    const bool try_far = (from_parent & close_missing) | (s.prev == close_c);
+    const bool try_far = (enter & close_missing) | (s.prev == close_c);
     const bool go_far = try_far & far_in & (far_c <= N);
     bool up = !(go_close | go_far);
+    bool far_next = go_far;
     int32_t child = curr;        // node being returned from
     int32_t anc_id = curr >> 1;  // node being returned to
     int32_t next = go_close ? close_c : far_c;
@@ -370,6 +410,7 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
                 const int32_t fa = child ^ 1;
                 const bool take_far = child_is_close & (sda * sda <= worst) & (fa <= N);
                 if (take_far) {
+                    far_next = true;
                     next = fa;
                     nprev = anc_id;
                     up = false;
@@ -389,6 +430,7 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     }
     s.prev = nprev;
     s.curr = next;
+    s.far_entry = far_next;
     return next;
 }
 
@@ -514,7 +556,14 @@ constexpr int max_block(int K) { return K >= 32 ? 256 : 1024; }
 #endif
 constexpr int min_waves(int K) { return K >= 64 ? KD_MIN_WAVES_K64 : 1; }
 
-template <int D, int K, int F, bool LEARNED>
+// Box tests: only on entering a far child (the side the split-plane test
+// lets through most loosely) whose subtree spans at least this many levels;
+// near the leaves a test costs about as much as the few nodes it could skip.
+#ifndef KD_BOX_MIN_HEIGHT
+#define KD_BOX_MIN_HEIGHT 3
+#endif
+
+template <int D, int K, int F, bool LEARNED, bool BOX>
 __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(TravArgs a) {
     const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);  // indexed by node id
     const int32_t* __restrict__ ids = node_ids<D>(g1, a.N);
@@ -580,7 +629,14 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
             int32_t idx;
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
             load_tree<D>(g1 + s.curr, c, idx, anc);
-            const int32_t next = lane_step<D, K, F>(s, c, idx, ids, anc, a.N);
+            bool skip = false;
+            if constexpr (BOX) {
+                // entering a far subtree of height >= KD_BOX_MIN_HEIGHT:
+                // leave it at once when its bounding box is out of range
+                if (s.far_entry && s.curr < a.box_below)
+                    skip = box_d2<D>(a.boxes, s.curr, s.q) > key_d2(s.L[K - 1]);
+            }
+            const int32_t next = lane_step<D, K, F>(s, c, idx, ids, anc, a.N, 0.0f, 0, skip);
             bool handed = false;
             if (++s.trips == a.heavy_trips && next != 0) {
                 // over budget: the cooperative kernel finishes this query,
@@ -817,10 +873,12 @@ __global__ void zero_u32(uint32_t* p, int n) {
 
 template <int D, int K>
 hipError_t launch_knn(const TravArgs& a, bool learned, int block, int grid, hipStream_t st) {
-    if (learned)
-        hipLaunchKernelGGL((knn_persistent<D, K, fused_levels(D), true>), dim3(grid), dim3(block), 0, st, a);
-    else
-        hipLaunchKernelGGL((knn_persistent<D, K, fused_levels(D), false>), dim3(grid), dim3(block), 0, st, a);
+    const bool box = a.boxes != nullptr;
+    constexpr int F = fused_levels(D);
+    if (learned && box) hipLaunchKernelGGL((knn_persistent<D, K, F, true, true>), dim3(grid), dim3(block), 0, st, a);
+    else if (learned) hipLaunchKernelGGL((knn_persistent<D, K, F, true, false>), dim3(grid), dim3(block), 0, st, a);
+    else if (box) hipLaunchKernelGGL((knn_persistent<D, K, F, false, true>), dim3(grid), dim3(block), 0, st, a);
+    else hipLaunchKernelGGL((knn_persistent<D, K, F, false, false>), dim3(grid), dim3(block), 0, st, a);
     return hipGetLastError();
 }
 
@@ -841,7 +899,7 @@ hipError_t dispatch_k(int K, const TravArgs& a, bool learned, int block, int gri
 template <int D>
 hipError_t occupancy_k(int K, int block, int* occ) {
     switch (K) {
-#define KD_OCC(KK) case KK: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, knn_persistent<D, KK, fused_levels(D), true>, block, 0);
+#define KD_OCC(KK) case KK: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, knn_persistent<D, KK, fused_levels(D), true, true>, block, 0);
         KD_OCC(1) KD_OCC(2) KD_OCC(4) KD_OCC(8) KD_OCC(16) KD_OCC(32) KD_OCC(64)
 #undef KD_OCC
     }
@@ -1240,6 +1298,18 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
 
     TravArgs a = {};
     a.nodes = t->d_nodes;
+    // subtree boxes unless the paper's rule is asked for, explicitly or by
+    // requesting its processed-node count
+    const bool use_boxes = plan.prune == 2 || (plan.prune == 0 && visited == nullptr);
+    a.boxes = use_boxes ? static_cast<const float*>(t->d_boxes) : nullptr;
+    {
+        // node ids of depth <= levels - KD_BOX_MIN_HEIGHT (levels =
+        // floor(log2 N) + 1): subtrees of height >= KD_BOX_MIN_HEIGHT
+        int levels = 0;
+        while (levels < 31 && (int64_t(1) << levels) <= t->N) ++levels;
+        const int e = levels - KD_BOX_MIN_HEIGHT + 1;
+        a.box_below = e <= 0 ? 1 : int32_t(1) << e;  // N <= 2^30: e <= 29
+    }
     a.N = int32_t(t->N);
     a.sq = sq;
     a.Q = uint32_t(Q);
