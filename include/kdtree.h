@@ -249,8 +249,8 @@ typedef struct kd_batch_s* kd_batch;
 /* Validates the jobs, allocates the batch's scratch (owned by the batch) and
  * captures the whole pipeline into a hipGraph (on a private stream when
  * stream is NULL).  The job pointers are baked into the graph: they must stay
- * valid for the batch's lifetime.  opts (nullable): block, waves_per_cu and
- * sort_bits apply to every group. */
+ * valid for the batch's lifetime.  opts (nullable): block, waves_per_cu,
+ * sort_bits and prune apply to every group. */
 kd_status kd_batch_create(const kd_job* jobs, int n_jobs, const kd_opts* opts, kd_stream stream, kd_batch* out);
 /* Replays the captured graph on stream (asynchronous). */
 kd_status kd_batch_run(kd_batch b, kd_stream stream);

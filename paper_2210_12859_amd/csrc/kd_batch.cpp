@@ -105,6 +105,9 @@ kd_status kd_batch_create(const kd_job* jobs, int n_jobs, const kd_opts* opts, k
         auto& g = groups[{J.tree->dim, K}];
         BatchJob bj{};
         bj.nodes = J.tree->d_nodes;
+        // subtree boxes unless the paper's rule alone is asked for
+        bj.boxes = plan.prune == 1 ? nullptr : static_cast<const float*>(J.tree->d_boxes);
+        bj.box_below = box_id_limit(J.tree->N);
         bj.queries = J.queries;
         bj.out_idx = J.out_idx;
         bj.out_d2 = J.out_d2;

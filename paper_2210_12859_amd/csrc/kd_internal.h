@@ -60,6 +60,19 @@ struct alignas(4 * rec_words(D)) TreeRec {
 // so a box is two aligned dwordx4 loads).
 constexpr int box_words(int D) { return D == 2 ? 4 : 8; }
 inline size_t box_buffer_bytes(int D, int64_t N) { return size_t(N + 2) * 4 * size_t(box_words(D)); }
+// Box tests are made for subtrees spanning at least this many levels (near the
+// leaves a test costs about as much as the few nodes it could skip).
+#ifndef KD_BOX_MIN_HEIGHT
+#define KD_BOX_MIN_HEIGHT 3
+#endif
+// First node id whose subtree spans fewer than KD_BOX_MIN_HEIGHT levels
+// (ids of depth <= levels - KD_BOX_MIN_HEIGHT, levels = floor(log2 N) + 1).
+inline int32_t box_id_limit(int64_t N) {
+    int levels = 0;
+    while (levels < 31 && (int64_t(1) << levels) <= N) ++levels;
+    const int e = levels - KD_BOX_MIN_HEIGHT + 1;
+    return e <= 0 ? 1 : int32_t(1) << e;  // N <= 2^30: e <= 29
+}
 
 // Tuned launch parameters kept with a tree (filled by kd_autotune).
 struct TuneEntry {
@@ -143,6 +156,8 @@ int k_template(int k);
 // class are laid out back to back in a class slot space.
 struct BatchJob {
     const void* nodes;       // TreeRec<D>[N + 2], record of node id i at index i
+    const float* boxes;      // subtree bounding boxes of the tree (see box_words)
+    int32_t box_below;       // boxes are tested for node ids below this
     const float* queries;    // caller [Q][D]
     int32_t* out_idx;        // caller [Q][k]
     float* out_d2;           // caller [Q][k] or NULL

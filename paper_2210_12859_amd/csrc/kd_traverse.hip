@@ -556,12 +556,9 @@ constexpr int max_block(int K) { return K >= 32 ? 256 : 1024; }
 #endif
 constexpr int min_waves(int K) { return K >= 64 ? KD_MIN_WAVES_K64 : 1; }
 
-// Box tests: only on entering a far child (the side the split-plane test
-// lets through most loosely) whose subtree spans at least this many levels;
-// near the leaves a test costs about as much as the few nodes it could skip.
-#ifndef KD_BOX_MIN_HEIGHT
-#define KD_BOX_MIN_HEIGHT 3
-#endif
+// Box tests are made only on entering a far child (the side the split-plane
+// test lets through most loosely) whose subtree spans at least
+// KD_BOX_MIN_HEIGHT levels.
 
 template <int D, int K, int F, bool LEARNED, bool BOX>
 __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(TravArgs a) {
@@ -694,6 +691,8 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
 #endif
 struct CoopArgs {
     const void* nodes;
+    const float* boxes;      // subtree bounding boxes, or NULL (split planes only)
+    int32_t box_below;       // boxes are tested for node ids below this
     int32_t N;
     int T;                   // subtree depth: levels - 1 - KD_COOP_SUB_LEVELS, at least 0
     const float* queries;    // caller [Q][D]
@@ -792,6 +791,7 @@ __global__ __launch_bounds__(256) void knn_coop(CoopArgs a) {
                     if (lane == l) {
                         s.curr = tcurr;
                         s.prev = tcurr >> 1;
+                        s.far_entry = true;  // its box is tested on entry
                         stop = tcurr >> 1;
                     }
                     tprev = tcurr;
@@ -833,7 +833,9 @@ __global__ __launch_bounds__(256) void knn_coop(CoopArgs a) {
                 int32_t idx;
                 float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
                 load_tree<D>(g1 + s.curr, c, idx, anc);
-                lane_step<D, K, fused_levels(D), true>(s, c, idx, ids, anc, a.N, bound, stop);
+                const bool skip = a.boxes != nullptr && s.far_entry && s.curr < a.box_below &&
+                                  box_d2<D>(a.boxes, s.curr, s.q) > fminf(key_d2(s.L[K - 1]), bound);
+                lane_step<D, K, fused_levels(D), true>(s, c, idx, ids, anc, a.N, bound, stop, skip);
                 if (s.curr == stop) s.curr = 0;
             }
             // the wave-wide bound is refreshed every 8 trips (a stale bound
@@ -1006,6 +1008,8 @@ struct BatchArgs {
 template <int D, int K>
 struct JobLane {
     const TreeRec<D>* g1;  // the lane's tree, indexed by node id
+    const float* boxes;    // its subtree bounding boxes (NULL: split planes only)
+    int32_t box_below;
     const int32_t* ids;    // its caller-index array (records without index)
     int32_t N;
     int32_t k;
@@ -1019,6 +1023,8 @@ __device__ __forceinline__ void batch_start(Lane<D, K>& s, JobLane<D, K>& j, con
                                             const BRec& r) {
     const BatchJob& J = jobs[r.job];
     j.g1 = reinterpret_cast<const TreeRec<D>*>(J.nodes);
+    j.boxes = J.boxes;
+    j.box_below = J.box_below;
     j.ids = node_ids<D>(j.g1, J.N);
     j.N = J.N;
     j.k = J.k;
@@ -1127,7 +1133,10 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
             int32_t idx;
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
             load_tree<D>(j.g1 + s.curr, c, idx, anc);
-            const int32_t next = lane_step<D, K, F>(s, c, idx, j.ids, anc, j.N);
+            // subtree box test as in knn_persistent (jobs may mix rules)
+            const bool skip = s.far_entry && s.curr < j.box_below && j.boxes != nullptr &&
+                              box_d2<D>(j.boxes, s.curr, s.q) > key_d2(s.L[K - 1]);
+            const int32_t next = lane_step<D, K, F>(s, c, idx, j.ids, anc, j.N, 0.0f, 0, skip);
             if (next == 0) {
                 batch_finish<D, K>(s, j);
             }
@@ -1302,14 +1311,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     // requesting its processed-node count
     const bool use_boxes = plan.prune == 2 || (plan.prune == 0 && visited == nullptr);
     a.boxes = use_boxes ? static_cast<const float*>(t->d_boxes) : nullptr;
-    {
-        // node ids of depth <= levels - KD_BOX_MIN_HEIGHT (levels =
-        // floor(log2 N) + 1): subtrees of height >= KD_BOX_MIN_HEIGHT
-        int levels = 0;
-        while (levels < 31 && (int64_t(1) << levels) <= t->N) ++levels;
-        const int e = levels - KD_BOX_MIN_HEIGHT + 1;
-        a.box_below = e <= 0 ? 1 : int32_t(1) << e;  // N <= 2^30: e <= 29
-    }
+    a.box_below = box_id_limit(t->N);
     a.N = int32_t(t->N);
     a.sq = sq;
     a.Q = uint32_t(Q);
@@ -1362,6 +1364,8 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
         // the device; waves beyond it exit at once)
         CoopArgs c = {};
         c.nodes = t->d_nodes;
+        c.boxes = a.boxes;
+        c.box_below = a.box_below;
         c.N = int32_t(t->N);
         int levels = 0;
         while (levels < 31 && (int64_t(1) << levels) <= t->N) ++levels;  // floor(log2 N) + 1
