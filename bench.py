@@ -39,7 +39,9 @@ WORKLOADS = {
     "gmm64-1m": "N=1,048,576 float32 3-D points from a 64-cluster Gaussian mixture (sigma 0.01); Q=1,048,576 from the same mixture",
     "uniform-16k": "N=16,384 uniform float32 3-D points; Q=16,384 uniform queries",
     "clustered-10m": "N=10,000,000 float32 3-D points, 256-cluster mixture (sigma log-uniform 0.002-0.05); Q=10,000,000 (90% mixture, 10% uniform)",
+    "shells-100m": "N=100,000,000 float32 3-D points on 1000 sphere shells (radius 0.01-0.1, radial noise 1e-4); Q=100,000,000 near the shells",
 }
+DEFAULT_RADIUS = {"shells-100m": 0.005}  # else unbounded
 
 
 def log(msg):
@@ -104,13 +106,13 @@ def bench_boxes(kd, tree, q, oi, od, k, args, plain_ms):
     dev = q.device
     bi = torch.empty_like(oi)
     bd = torch.empty_like(od)
-    kd.kd_knn(tree, q, k, out_idx=bi, out_d2=bd)
-    _, _, vis = kd.kd_knn_ex(tree, q, k, want_visited=True, opts={"prune": 2})
+    kd.kd_knn(tree, q, k, args.max_radius, out_idx=bi, out_d2=bd)
+    _, _, vis = kd.kd_knn_ex(tree, q, k, args.max_radius, want_visited=True, opts={"prune": 2})
     torch.cuda.synchronize()
     identical = bool(torch.equal(bi, oi) and torch.equal(bd.view(torch.int32), od.view(torch.int32)))
     entered = int(vis.to(torch.int64).sum().item())
     for _ in range(args.warmup):
-        kd.kd_knn(tree, q, k, out_idx=bi, out_d2=bd)
+        kd.kd_knn(tree, q, k, args.max_radius, out_idx=bi, out_d2=bd)
     torch.cuda.synchronize()
     kd.kd_timing_enable(True)
     kd.kd_timing_collect("traverse")
@@ -119,7 +121,7 @@ def bench_boxes(kd, tree, q, oi, od, k, args, plain_ms):
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(args.steps):
-        kd.kd_knn(tree, q, k, out_idx=bi, out_d2=bd)
+        kd.kd_knn(tree, q, k, args.max_radius, out_idx=bi, out_d2=bd)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
@@ -149,13 +151,13 @@ def bench_learned(kd, datagen, tree, q, oi, od, k, args, plain_visited, plain_ms
     li = torch.empty_like(oi)
     ld = torch.empty_like(od)
     vis = torch.empty(q.shape[0], dtype=torch.int32, device=dev)
-    _, _, _, st = kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld, visited=vis, want_stats=True,
-                                    opts=PLAIN)
+    _, _, _, st = kd.kd_knn_learned(tree, model, q, k, args.max_radius, out_idx=li, out_d2=ld, visited=vis,
+                                    want_stats=True, opts=PLAIN)
     torch.cuda.synchronize()
     identical = bool(torch.equal(li, oi) and torch.equal(ld.view(torch.int32), od.view(torch.int32)))
     lvis = int(vis.to(torch.int64).sum().item())
     for _ in range(args.warmup):
-        kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld, opts=PLAIN)
+        kd.kd_knn_learned(tree, model, q, k, args.max_radius, out_idx=li, out_d2=ld, opts=PLAIN)
     torch.cuda.synchronize()
     kd.kd_timing_enable(True)
     for name in ("sort", "mlp", "traverse", "fallback"):
@@ -165,7 +167,7 @@ def bench_learned(kd, datagen, tree, q, oi, od, k, args, plain_visited, plain_ms
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(args.steps):
-        kd.kd_knn_learned(tree, model, q, k, out_idx=li, out_d2=ld, opts=PLAIN)
+        kd.kd_knn_learned(tree, model, q, k, args.max_radius, out_idx=li, out_d2=ld, opts=PLAIN)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
@@ -250,6 +252,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform-1m", choices=sorted(WORKLOADS))
     ap.add_argument("--k", type=int, default=8)
+    ap.add_argument("--max-radius", type=float, default=None,
+                    help="search radius (default: 0.005 for shells-100m, else unbounded)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-radius variant")
     ap.add_argument("--no-boxes", action="store_true", help="skip the default (bounding-box) pruning variant")
@@ -275,6 +279,8 @@ def main():
     import paper_2210_12859_amd as kd
     from paper_2210_12859_amd import datagen
 
+    if args.max_radius is None:
+        args.max_radius = DEFAULT_RADIUS.get(args.workload, math.inf)
     dev = torch.device("cuda:0")
     k = args.k
     log(f"workload {args.workload} k={k}: generating inputs")
@@ -290,13 +296,13 @@ def main():
     vis = torch.empty(Q, dtype=torch.int32, device=dev)
 
     # processed nodes per query (deterministic; equals the oracle's count)
-    kd.kd_knn_ex(tree, q, k, out_idx=oi, out_d2=od, visited=vis)
+    kd.kd_knn_ex(tree, q, k, args.max_radius, out_idx=oi, out_d2=od, visited=vis)
     torch.cuda.synchronize()
     visited_total = int(vis.to(torch.int64).sum().item())
     log(f"mean processed nodes/query = {visited_total / Q:.2f}")
 
     for _ in range(args.warmup):
-        kd.kd_knn_ex(tree, q, k, out_idx=oi, out_d2=od, opts=PLAIN)
+        kd.kd_knn_ex(tree, q, k, args.max_radius, out_idx=oi, out_d2=od, opts=PLAIN)
     torch.cuda.synchronize()
     kd.kd_timing_enable(True)
     kd.kd_timing_collect("traverse")
@@ -306,7 +312,7 @@ def main():
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
-        kd.kd_knn_ex(tree, q, k, out_idx=oi, out_d2=od, opts=PLAIN)
+        kd.kd_knn_ex(tree, q, k, args.max_radius, out_idx=oi, out_d2=od, opts=PLAIN)
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
@@ -335,7 +341,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}; kNN k={k}, maxRadius=inf",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}; kNN k={k}, maxRadius={args.max_radius:g}",
                    "variant": "plain", "k": k, "N": N, "Q": Q, "dim": D},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,

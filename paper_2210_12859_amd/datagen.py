@@ -107,6 +107,8 @@ def training_queries(name: str, n: int = 1 << 20, seed: int = 7) -> np.ndarray:
         return gmm(n, 3, seed)
     if name == "clustered-10m":
         return clustered_lr_queries(n, seed)
+    if name == "shells-100m":
+        return shells(n, seed)
     raise KeyError(name)
 
 
@@ -120,4 +122,6 @@ def workload(name: str):
         return gmm(1 << 20, 3, 0), gmm(1 << 20, 3, 1)
     if name == "clustered-10m":
         return clustered_lr_points(10_000_000, 0), clustered_lr_queries(10_000_000, 1)
+    if name == "shells-100m":
+        return shells(100_000_000, 0), shells(100_000_000, 1)
     raise KeyError(name)
