@@ -151,6 +151,20 @@ kd_status kd_knn_ex(kd_tree t, const float* queries, int64_t Q, int k, float max
                     int32_t* out_idx, float* out_d2, uint32_t* visited,
                     const kd_opts* opts, kd_stream stream);
 
+/* Device scratch of one query call.  kd_fcp, kd_knn, kd_knn_ex,
+ * kd_knn_learned and kd_knn_with_radius use a per-stream workspace that the
+ * library allocates on first use and keeps (growing it when a larger call
+ * comes) until the process ends; this returns the bytes such a call of Q
+ * queries needs, an upper bound over dim and launch options (query records,
+ * sort buffers, work counters, hand-off rows).
+ *   k     : validated (1..KD_MAX_K); the size does not depend on it.
+ *   flags : 0, or KD_WS_LEARNED for the per-query initial radii of the
+ *           learned-radius calls.
+ *   bytes : host; receives the size (0 for Q = 0).
+ * Host only: no device call, no allocation. */
+#define KD_WS_LEARNED 1
+kd_status kd_workspace_size(int64_t Q, int k, int flags, size_t* bytes);
+
 /* ------------------------------------------------- learned initial radius */
 
 /* A small MLP (3 -> 64 -> 64 -> 1, ReLU; bfloat16 operands, float32

@@ -89,6 +89,7 @@ def lib():
         "kd_autotune": ([P, P, i64, i32, f32, P, P, P], i32),
         "kd_tree_get_tuned": ([P, i32, P], i32),
         "kd_tree_set_tuned": ([P, i32, P], i32),
+        "kd_workspace_size": ([i64, i32, i32, P], i32),
         "kd_timing_enable": ([i32], i32),
         "kd_timing_collect": ([ctypes.c_char_p, P, P], i32),
         "kd_status_str": ([i32], ctypes.c_char_p),
@@ -369,6 +370,14 @@ def kd_knn_with_radius(tree: Tree, r0, queries, k, max_radius=math.inf, out_idx=
                                     float(max_radius), _ptr(out_idx), _ptr(out_d2), _ptr(visited), _ptr(fell_back),
                                     _opts(opts), _stream_handle(stream)))
     return out_idx, out_d2, visited, fell_back
+
+
+def kd_workspace_size(Q: int, k: int, learned: bool = False) -> int:
+    """Device scratch bytes a query call of Q queries needs (upper bound over
+    dim and options; kept per stream by the library).  Host only."""
+    b = ctypes.c_size_t()
+    _check(lib().kd_workspace_size(int(Q), int(k), 1 if learned else 0, ctypes.byref(b)))
+    return b.value
 
 
 def kd_mlp_predict(model: Model, queries, out=None, stream=None):

@@ -360,6 +360,20 @@ kd_status kd_tree_free(kd_tree t) {
     return KD_OK;
 }
 
+kd_status kd_workspace_size(int64_t Q, int k, int flags, size_t* bytes) {
+    if (!bytes) return set_error(KD_EINVAL, "kd_workspace_size: bytes is NULL");
+    if (Q < 0 || Q >= (int64_t(1) << 31)) return set_error(KD_EINVAL, "kd_workspace_size: Q out of range [0, 2^31)");
+    if (k < 1 || k > KD_MAX_K) return set_error(KD_EINVAL, "kd_workspace_size: k out of range [1, 64]");
+    if (flags & ~KD_WS_LEARNED) return set_error(KD_EINVAL, "kd_workspace_size: unknown flags");
+    // upper bound over dim (D = 4 has the largest records) and launch options
+    // (sorted, with the hand-off rows)
+    size_t b = 0;
+    for (int dim = 2; dim <= 4; ++dim)
+        b = std::max(b, query_scratch_bytes(Q, dim, true, (flags & KD_WS_LEARNED) != 0, true));
+    *bytes = Q == 0 ? 0 : b;
+    return KD_OK;
+}
+
 kd_status kd_tree_info(kd_tree t, int64_t* N, int* dim, float* lo4, float* hi4) {
     if (!t) return set_error(KD_EINVAL, "kd_tree_info: tree is NULL");
     if (N) *N = t->N;

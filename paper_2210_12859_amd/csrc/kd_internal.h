@@ -189,6 +189,8 @@ size_t batch_rec_bytes();
 size_t batch_cursor_bytes();  // work cursors of one class launch
 // Morton reorder of query slots (kd_sort.hip)
 size_t sort_scratch_bytes(int64_t Q, int dim);
+// device scratch of one kd_knn-family call (kd_traverse.hip)
+size_t query_scratch_bytes(int64_t Q, int dim, bool sorted, bool learned, bool handoff);
 // Writes the queries as traversal records (NodeRec<dim>[Q]) into sq, in
 // Morton order on the top sort_bits bits (0: caller order), and clears
 // zero[0..nzero) on the way.  ws holds sort_scratch_bytes(Q, dim) when sort_bits > 0.

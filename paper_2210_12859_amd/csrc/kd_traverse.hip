@@ -1250,6 +1250,19 @@ int k_template(int k) {
     return K;
 }
 
+// Per-stream scratch of one query call, laid out as run_knn uses it:
+// [range cursors | restart count | hand-off count] (256 KB + 4 KB), traversal
+// records, sort ping-pong buffers and histograms, initial radii (learned),
+// hand-off rows.
+size_t query_scratch_bytes(int64_t Q, int dim, bool sorted, bool learned, bool handoff) {
+    const size_t cursor_bytes = size_t(MAX_GROUPS) * CURSOR_STRIDE * 4;
+    const size_t head = cursor_bytes + 4096;
+    const size_t sq_bytes = (size_t(Q) * rec_bytes(dim) + 255) & ~size_t(255);
+    const size_t sort_bytes = sorted ? sort_scratch_bytes(Q, dim) : 0;
+    const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
+    return head + sq_bytes + sort_bytes + (learned ? q4 : 0) + (handoff ? q4 : 0);
+}
+
 kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan, int32_t* out_idx,
                   float* out_d2, uint32_t* visited, kd_stream stream, const LearnedSpec* learned,
                   uint32_t* fallbacks_out) {
@@ -1268,7 +1281,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
     const size_t learn_bytes = learned ? q4 : 0;
     const size_t heavy_bytes = handoff ? q4 : 0;
-    kd_status s = scratch(stream, head + sq_bytes + sort_bytes + learn_bytes + heavy_bytes, &ws);
+    kd_status s = scratch(stream, query_scratch_bytes(Q, t->dim, plan.sort_bits > 0, learned != nullptr, handoff), &ws);
     if (s != KD_OK) return s;
     char* base = static_cast<char*>(ws);
     uint32_t* counter1 = reinterpret_cast<uint32_t*>(base);

@@ -112,3 +112,20 @@ def test_host_builder_equals_oracle_1m(oracle_lib):
     from paper_2210_12859_amd import datagen
     P_, _ = datagen.workload("uniform-1m")
     assert np.array_equal(kd.kd_build_order_host(P_), oracle_lib.build_tree(P_))
+
+
+def test_workspace_size():
+    """kd_workspace_size: host only; grows with Q, covers the traversal
+    records (32 B per query for D = 4) and the sort buffers, adds the
+    per-query radii for learned calls, validates its arguments."""
+    assert kd.kd_workspace_size(0, 8) == 0
+    a = kd.kd_workspace_size(1 << 20, 8)
+    b = kd.kd_workspace_size(1 << 21, 8)
+    assert b > a >= (1 << 20) * (32 + 2 * (4 + 32))
+    assert kd.kd_workspace_size(1 << 20, 1) == a == kd.kd_workspace_size(1 << 20, 64)
+    assert kd.kd_workspace_size(1 << 20, 8, learned=True) >= a + (1 << 20) * 4
+    L = kd.lib()
+    out = ctypes.c_size_t()
+    for Q, k, flags in [(-1, 8, 0), (1 << 31, 8, 0), (10, 0, 0), (10, 65, 0), (10, 8, 2)]:
+        assert L.kd_workspace_size(Q, k, flags, ctypes.byref(out)) == kd.KD_EINVAL
+    assert L.kd_workspace_size(10, 8, 0, None) == kd.KD_EINVAL
