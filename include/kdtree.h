@@ -65,7 +65,14 @@ typedef enum {
 typedef struct {
     int block;       /* threads per workgroup: 256, 512 or 1024 (k > 16: 256); 64, 128
                         also accepted; 0 = default (256) */
-    int lds_levels;  /* reserved, ignored (0 or -1) */
+    int lds_levels;  /* top tree levels staged in each workgroup's LDS at launch
+                        (node ids < 2^L, paper level order): steps at those
+                        nodes read LDS instead of global memory.  0 or -1 =
+                        none (default; measured no faster: the top levels stay
+                        in L1/L2), 1..12, at most 64 KB of records (dim 4:
+                        L <= 11).  kd_fcp / kd_knn / kd_knn_ex only; the
+                        learned, batched and cooperative kernels read global
+                        memory. */
     int sort_bits;   /* Morton bits the queries are sorted on before traversal:
                         0 keeps the caller's order; 1..32 is rounded up to a
                         whole byte (8, 16, 24, 32); -1 = default (16) */

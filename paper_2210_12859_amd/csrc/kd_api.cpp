@@ -261,7 +261,9 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     if (use.heavy_trips < -1) return set_error(KD_EINVAL, "opts.heavy_trips must be -1, 0 or positive");
     if (use.block != 64 && use.block != 128 && use.block != 256 && use.block != 512 && use.block != 1024)
         return set_error(KD_EINVAL, "opts.block must be 64, 128, 256, 512 or 1024");
-    if (use.lds_levels > 13) return set_error(KD_EINVAL, "opts.lds_levels must be <= 13");
+    if (use.lds_levels > 12) return set_error(KD_EINVAL, "opts.lds_levels must be <= 12");
+    if (t && use.lds_levels > 0 && (size_t(1) << use.lds_levels) * 4 * size_t(rec_words(t->dim)) > 65536)
+        return set_error(KD_EINVAL, "opts.lds_levels: the staged levels exceed 64 KB of LDS (dim 4: at most 11)");
     if (use.sort_bits > 32) return set_error(KD_EINVAL, "opts.sort_bits must be in 0..32 or -1");
     use.sort_bits = ((use.sort_bits + 7) / 8) * 8;  // the radix sort takes whole bytes
     if (use.waves_per_cu < 1 || use.waves_per_cu > 32) return set_error(KD_EINVAL, "opts.waves_per_cu must be in 1..32");

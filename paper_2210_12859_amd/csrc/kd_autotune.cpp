@@ -61,11 +61,13 @@ kd_status kd_autotune(kd_tree t, const float* sample_q, int64_t Qs, int k, float
     const int waves[] = {8, 12, 16, 24, 32};
     const int sorts[] = {0, 16, 24, 32};
     const int prunes[] = {1, 2};
+    const int ldsl[] = {0, 10};  // top levels in LDS (dim 4: 32 KB of records)
     for (int b : blocks) {
         if (K >= 32 && b > 256) continue;
         for (int w : waves)
             for (int sb : sorts)
-                for (int pr : prunes) cands.push_back(kd_opts{b, 0, sb, w, 0, pr});
+                for (int pr : prunes)
+                    for (int l : ldsl) cands.push_back(kd_opts{b, l, sb, w, 0, pr});
     }
     int32_t* idx = nullptr;
     float* d2 = nullptr;

@@ -144,7 +144,7 @@ struct QueryPlan {
     int K = 1;          // compiled list size >= k
     float R2 = 0;
     int block = 256;
-    int lds_levels = 10;
+    int lds_levels = 0;   // top tree levels staged in LDS (plain queries), 0 = none
     int sort_bits = 32;
     int waves_per_cu = 8;
     int heavy_trips = 0;  // trip budget before the cooperative hand-off, 0 = none

@@ -46,6 +46,8 @@
 //     a fixed, fully unrolled network behind a wave-uniform skip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "kd_internal.h"
@@ -61,6 +63,7 @@ struct TravArgs {
     const void* nodes;       // TreeRec<D>[N + 2], record of node id i at index i
     const float* boxes;      // [N + 2][box_words(D)] subtree bounding boxes (BOX kernels)
     int32_t box_below;       // boxes are tested for node ids below this (subtrees tall enough)
+    int32_t lds_below;       // LDS kernels: records of node ids 1 .. lds_below-1 are staged in LDS
     int32_t N;
     const void* sq;          // NodeRec<D>[Q]: queries in traversal order, .idx = caller row
     uint32_t Q;              // query slots
@@ -560,11 +563,21 @@ constexpr int min_waves(int K) { return K >= 64 ? KD_MIN_WAVES_K64 : 1; }
 // test lets through most loosely) whose subtree spans at least
 // KD_BOX_MIN_HEIGHT levels.
 
-template <int D, int K, int F, bool LEARNED, bool BOX>
+// LDS kernels stage the records of the top tree levels (node ids below
+// a.lds_below, at most 64 KB) in the workgroup's LDS at launch; steps at those
+// nodes read them from there.  The traversal itself is unchanged.
+extern __shared__ uint4 kd_lds_nodes[];
+
+template <int D, int K, int F, bool LEARNED, bool BOX, bool LDSN>
 __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(TravArgs a) {
     const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);  // indexed by node id
     const int32_t* __restrict__ ids = node_ids<D>(g1, a.N);
     const NodeRec<D>* __restrict__ sq = reinterpret_cast<const NodeRec<D>*>(a.sq);
+    TreeRec<D>* lrec = reinterpret_cast<TreeRec<D>*>(kd_lds_nodes);  // indexed by node id
+    if constexpr (LDSN) {
+        for (int32_t i = int32_t(threadIdx.x) + 1; i < a.lds_below; i += int32_t(blockDim.x)) lrec[i] = g1[i];
+        __syncthreads();
+    }
 
     const uint32_t lane = __lane_id();
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
@@ -625,7 +638,8 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
             float c[D];
             int32_t idx;
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
-            load_tree<D>(g1 + s.curr, c, idx, anc);
+            if (LDSN && s.curr < a.lds_below) load_tree<D>(lrec + s.curr, c, idx, anc);
+            else load_tree<D>(g1 + s.curr, c, idx, anc);
             bool skip = false;
             if constexpr (BOX) {
                 // entering a far subtree of height >= KD_BOX_MIN_HEIGHT:
@@ -873,55 +887,66 @@ __global__ void zero_u32(uint32_t* p, int n) {
 }
 
 
+// lds_bytes > 0: the LDS kernels (plain queries only; the learned kernels
+// read every node from global memory)
 template <int D, int K>
-hipError_t launch_knn(const TravArgs& a, bool learned, int block, int grid, hipStream_t st) {
+hipError_t launch_knn(const TravArgs& a, bool learned, int block, int grid, size_t lds_bytes, hipStream_t st) {
     const bool box = a.boxes != nullptr;
     constexpr int F = fused_levels(D);
-    if (learned && box) hipLaunchKernelGGL((knn_persistent<D, K, F, true, true>), dim3(grid), dim3(block), 0, st, a);
-    else if (learned) hipLaunchKernelGGL((knn_persistent<D, K, F, true, false>), dim3(grid), dim3(block), 0, st, a);
-    else if (box) hipLaunchKernelGGL((knn_persistent<D, K, F, false, true>), dim3(grid), dim3(block), 0, st, a);
-    else hipLaunchKernelGGL((knn_persistent<D, K, F, false, false>), dim3(grid), dim3(block), 0, st, a);
+    const dim3 g(grid), b(block);
+    if (learned && box) hipLaunchKernelGGL((knn_persistent<D, K, F, true, true, false>), g, b, 0, st, a);
+    else if (learned) hipLaunchKernelGGL((knn_persistent<D, K, F, true, false, false>), g, b, 0, st, a);
+    else if (lds_bytes && box) hipLaunchKernelGGL((knn_persistent<D, K, F, false, true, true>), g, b, lds_bytes, st, a);
+    else if (lds_bytes) hipLaunchKernelGGL((knn_persistent<D, K, F, false, false, true>), g, b, lds_bytes, st, a);
+    else if (box) hipLaunchKernelGGL((knn_persistent<D, K, F, false, true, false>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((knn_persistent<D, K, F, false, false, false>), g, b, 0, st, a);
     return hipGetLastError();
 }
 
 template <int D>
-hipError_t dispatch_k(int K, const TravArgs& a, bool learned, int block, int grid, hipStream_t st) {
+hipError_t dispatch_k(int K, const TravArgs& a, bool learned, int block, int grid, size_t lds_bytes, hipStream_t st) {
     switch (K) {
-        case 1: return launch_knn<D, 1>(a, learned, block, grid, st);
-        case 2: return launch_knn<D, 2>(a, learned, block, grid, st);
-        case 4: return launch_knn<D, 4>(a, learned, block, grid, st);
-        case 8: return launch_knn<D, 8>(a, learned, block, grid, st);
-        case 16: return launch_knn<D, 16>(a, learned, block, grid, st);
-        case 32: return launch_knn<D, 32>(a, learned, block, grid, st);
-        case 64: return launch_knn<D, 64>(a, learned, block, grid, st);
+        case 1: return launch_knn<D, 1>(a, learned, block, grid, lds_bytes, st);
+        case 2: return launch_knn<D, 2>(a, learned, block, grid, lds_bytes, st);
+        case 4: return launch_knn<D, 4>(a, learned, block, grid, lds_bytes, st);
+        case 8: return launch_knn<D, 8>(a, learned, block, grid, lds_bytes, st);
+        case 16: return launch_knn<D, 16>(a, learned, block, grid, lds_bytes, st);
+        case 32: return launch_knn<D, 32>(a, learned, block, grid, lds_bytes, st);
+        case 64: return launch_knn<D, 64>(a, learned, block, grid, lds_bytes, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <int D>
-hipError_t occupancy_k(int K, int block, int* occ) {
+hipError_t occupancy_k(int K, int block, size_t lds_bytes, int* occ) {
     switch (K) {
-#define KD_OCC(KK) case KK: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, knn_persistent<D, KK, fused_levels(D), true, true>, block, 0);
+#define KD_OCC(KK)                                                                                              \
+    case KK:                                                                                                    \
+        return lds_bytes ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                        \
+                               occ, knn_persistent<D, KK, fused_levels(D), false, true, true>, block, lds_bytes) \
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                        \
+                               occ, knn_persistent<D, KK, fused_levels(D), true, true, false>, block, 0);
         KD_OCC(1) KD_OCC(2) KD_OCC(4) KD_OCC(8) KD_OCC(16) KD_OCC(32) KD_OCC(64)
 #undef KD_OCC
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t occupancy(int D, int K, int block, int* occ) {
+hipError_t occupancy(int D, int K, int block, size_t lds_bytes, int* occ) {
     switch (D) {
-        case 2: return occupancy_k<2>(K, block, occ);
-        case 3: return occupancy_k<3>(K, block, occ);
-        case 4: return occupancy_k<4>(K, block, occ);
+        case 2: return occupancy_k<2>(K, block, lds_bytes, occ);
+        case 3: return occupancy_k<3>(K, block, lds_bytes, occ);
+        case 4: return occupancy_k<4>(K, block, lds_bytes, occ);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t dispatch_dk(int D, int K, const TravArgs& a, bool learned, int block, int grid, hipStream_t st) {
+hipError_t dispatch_dk(int D, int K, const TravArgs& a, bool learned, int block, int grid, size_t lds_bytes,
+                       hipStream_t st) {
     switch (D) {
-        case 2: return dispatch_k<2>(K, a, learned, block, grid, st);
-        case 3: return dispatch_k<3>(K, a, learned, block, grid, st);
-        case 4: return dispatch_k<4>(K, a, learned, block, grid, st);
+        case 2: return dispatch_k<2>(K, a, learned, block, grid, lds_bytes, st);
+        case 3: return dispatch_k<3>(K, a, learned, block, grid, lds_bytes, st);
+        case 4: return dispatch_k<4>(K, a, learned, block, grid, lds_bytes, st);
     }
     return hipErrorInvalidValue;
 }
@@ -1325,6 +1350,13 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     const bool use_boxes = plan.prune == 2 || (plan.prune == 0 && visited == nullptr);
     a.boxes = use_boxes ? static_cast<const float*>(t->d_boxes) : nullptr;
     a.box_below = box_id_limit(t->N);
+    // top levels in LDS (plain queries): ids 1 .. min(2^L, N + 1) - 1
+    size_t lds_bytes = 0;
+    if (plan.lds_levels > 0 && !learned) {
+        const int64_t below = std::min<int64_t>(int64_t(1) << plan.lds_levels, t->N + 1);
+        a.lds_below = int32_t(below);
+        lds_bytes = size_t(below) * 4 * size_t(rec_words(t->dim));
+    }
     a.N = int32_t(t->N);
     a.sq = sq;
     a.Q = uint32_t(Q);
@@ -1354,7 +1386,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     if (plan.K >= 32 && block > 256) block = 256;
     const int waves_per_block = block / 64;
     int occ = 0;
-    e = occupancy(t->dim, plan.K, block, &occ);
+    e = occupancy(t->dim, plan.K, block, lds_bytes, &occ);
     if (e != hipSuccess) return hip_error(e, "occupancy query");
     int64_t per_cu = plan.waves_per_cu / waves_per_block;
     if (per_cu < 1) per_cu = 1;
@@ -1368,7 +1400,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     hipEvent_t ev0;
     s = timing_begin(st, &ev0);
     if (s != KD_OK) return s;
-    e = dispatch_dk(t->dim, plan.K, a, learned != nullptr, block, int(grid), st);
+    e = dispatch_dk(t->dim, plan.K, a, learned != nullptr, block, int(grid), lds_bytes, st);
     if (e != hipSuccess) return hip_error(e, "knn_persistent launch");
     s = timing_end(st, ev0, "traverse");
     if (s != KD_OK) return s;

@@ -91,6 +91,8 @@ def test_c1_knn_entry_without_d2(c1, oracle_lib):
     dict(block=64, waves_per_cu=2), dict(block=256, waves_per_cu=32), dict(block=1024, waves_per_cu=32),
     dict(sort_bits=0), dict(sort_bits=1), dict(sort_bits=8), dict(sort_bits=12), dict(sort_bits=14),
     dict(sort_bits=15), dict(sort_bits=16), dict(sort_bits=24), dict(sort_bits=32),
+    dict(lds_levels=1), dict(lds_levels=6), dict(lds_levels=10), dict(lds_levels=12),
+    dict(lds_levels=10, block=1024, waves_per_cu=32),
 ])
 def test_c1_all_launch_options_identical(c1, oracle_lib, opts):
     P, Qs, tree, order = c1
