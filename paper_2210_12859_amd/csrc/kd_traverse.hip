@@ -64,6 +64,7 @@ struct TravArgs {
     const float* boxes;      // [N + 2][box_words(D)] subtree bounding boxes (BOX kernels)
     int32_t box_below;       // boxes are tested for node ids below this (subtrees tall enough)
     int32_t lds_below;       // LDS kernels: records of node ids 1 .. lds_below-1 are staged in LDS
+    uint32_t refill_min;     // idle lanes are refilled once at least this many are idle
     int32_t N;
     const void* sq;          // NodeRec<D>[Q]: queries in traversal order, .idx = caller row
     uint32_t Q;              // query slots
@@ -563,6 +564,17 @@ constexpr int min_waves(int K) { return K >= 64 ? KD_MIN_WAVES_K64 : 1; }
 // test lets through most loosely) whose subtree spans at least
 // KD_BOX_MIN_HEIGHT levels.
 
+// Idle lanes are refilled once at least refill_min of them are idle: the
+// refill's shuffles and list resets run for the whole wave, so waiting for a
+// few lanes amortises them at the cost of a few idle lane-trips.  Measured
+// (traversal ms, threshold 1 / 4): uniform-1m k = 8 0.689 / 0.698 with the
+// paper's rule, 0.679 / 0.654 with subtree boxes; fcp 0.258 / 0.250; k = 64
+// (boxes) 7.59 / 7.47; gmm64 k = 8 1.151 / 1.124; clustered-10m k = 16 (boxes)
+// 36.0 / 35.7.
+#ifndef KD_REFILL_MIN_BATCHED
+#define KD_REFILL_MIN_BATCHED 4
+#endif
+
 // LDS kernels stage the records of the top tree levels (node ids below
 // a.lds_below, at most 64 KB) in the workgroup's LDS at launch; steps at those
 // nodes read them from there.  The traversal itself is unchanged.
@@ -596,7 +608,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
     uint32_t restarts = 0;  // learned runs restarted from R2 by this lane
     for (;;) {
         const uint64_t need = wave_ballot(s.curr == 0);
-        if (need && !ws.exhausted) {
+        if (need && !ws.exhausted && uint32_t(__popcll(need)) >= a.refill_min) {
             const uint32_t n = __popcll(need);
             const uint32_t rank = __popcll(need & lt_mask);
             const uint32_t take1 = n < cn - cpos ? n : cn - cpos;
@@ -1122,7 +1134,7 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
     JobLane<D, K> j;
     for (;;) {
         const uint64_t need = wave_ballot(s.curr == 0);
-        if (need && !ws.exhausted) {
+        if (need && !ws.exhausted && __popcll(need) >= KD_REFILL_MIN_BATCHED) {
             const uint32_t n = __popcll(need);
             const uint32_t rank = __popcll(need & lt_mask);
             const uint32_t take1 = n < cn - cpos ? n : cn - cpos;
@@ -1350,6 +1362,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     const bool use_boxes = plan.prune == 2 || (plan.prune == 0 && visited == nullptr);
     a.boxes = use_boxes ? static_cast<const float*>(t->d_boxes) : nullptr;
     a.box_below = box_id_limit(t->N);
+    a.refill_min = (use_boxes || plan.K == 1) ? 4u : 1u;  // measured best, see KD_REFILL_MIN_BATCHED
     // top levels in LDS (plain queries): ids 1 .. min(2^L, N + 1) - 1
     size_t lds_bytes = 0;
     if (plan.lds_levels > 0 && !learned) {
