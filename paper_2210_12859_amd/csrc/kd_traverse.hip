@@ -98,8 +98,37 @@ __device__ __forceinline__ uint64_t make_key(float d2, int32_t idx) {
 __device__ __forceinline__ float key_d2(uint64_t key) { return __uint_as_float(uint32_t(key >> 32)); }
 
 // Sorted insertion of `key` (known to be < L[K-1]) into the ascending list L.
+#ifndef KD_INSERT_MED3
+#define KD_INSERT_MED3 1
+#endif
+__device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c) {
+    // the median-of-three form the compiler maps to one v_med3_u32
+    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    const uint32_t m = hi < c ? hi : c;
+    return lo > m ? lo : m;
+}
+
+// Slot j becomes key clamped to [L[j-1], L[j]] (64-bit order).  Its high
+// word (the d2 bits) is the median of the three high words, as the list is
+// sorted; its low word (the index) follows the two 64-bit comparisons.
 template <int K>
 __device__ __forceinline__ void list_insert(uint64_t (&L)[K], uint64_t key) {
+#if KD_INSERT_MED3
+    const uint32_t khi = uint32_t(key >> 32), klo = uint32_t(key);
+#pragma unroll
+    for (int j = K - 1; j > 0; --j) {
+        const bool lt_prev = key < L[j - 1];
+        const bool lt_here = key < L[j];
+        const uint32_t hi = med3_u32(uint32_t(L[j - 1] >> 32), khi, uint32_t(L[j] >> 32));
+        const uint32_t lo = lt_prev ? uint32_t(L[j - 1]) : (lt_here ? klo : uint32_t(L[j]));
+        L[j] = (uint64_t(hi) << 32) | lo;
+    }
+    {
+        const bool lt0 = key < L[0];
+        const uint32_t h0 = uint32_t(L[0] >> 32);
+        L[0] = (uint64_t(khi < h0 ? khi : h0) << 32) | (lt0 ? klo : uint32_t(L[0]));
+    }
+#else
 #pragma unroll
     for (int j = K - 1; j > 0; --j) {
         const bool lt_prev = key < L[j - 1];
@@ -107,6 +136,7 @@ __device__ __forceinline__ void list_insert(uint64_t (&L)[K], uint64_t key) {
         L[j] = lt_prev ? L[j - 1] : (lt_here ? key : L[j]);
     }
     L[0] = key < L[0] ? key : L[0];
+#endif
 }
 
 // Split dimension of node id n (1-based) is level mod D with level =
