@@ -40,6 +40,7 @@ WORKLOADS = {
     "uniform-16k": "N=16,384 uniform float32 3-D points; Q=16,384 uniform queries",
     "clustered-10m": "N=10,000,000 float32 3-D points, 256-cluster mixture (sigma log-uniform 0.002-0.05); Q=10,000,000 (90% mixture, 10% uniform)",
     "shells-100m": "N=100,000,000 float32 3-D points on 1000 sphere shells (radius 0.01-0.1, radial noise 1e-4); Q=100,000,000 near the shells",
+    "uniform4d-1m-q10m": "N=1,048,576 uniform float32 4-D points in [0,1)^4 (seed 0); Q=10,000,000 uniform queries (seed 1): the shape of the paper's Table 1",
 }
 DEFAULT_RADIUS = {"shells-100m": 0.005}  # else unbounded
 

@@ -275,8 +275,11 @@ __device__ __forceinline__ NodeRec<D> shfl_rec(const NodeRec<D>& r, int src) {
     return o;
 }
 
+// Fused "return to parent" levels per loop trip, at most the ancestor splits
+// a record holds (D = 2, 3: one; D = 4: three).  On 4-D uniform data three
+// levels beat one by 7-9 %.
 #ifndef KD_FUSED_LEVELS
-#define KD_FUSED_LEVELS 1
+#define KD_FUSED_LEVELS 3
 #endif
 constexpr int fused_levels(int D) { return KD_FUSED_LEVELS < rec_ancestors(D) ? KD_FUSED_LEVELS : rec_ancestors(D); }
 

@@ -124,4 +124,6 @@ def workload(name: str):
         return clustered_lr_points(10_000_000, 0), clustered_lr_queries(10_000_000, 1)
     if name == "shells-100m":
         return shells(100_000_000, 0), shells(100_000_000, 1)
+    if name == "uniform4d-1m-q10m":
+        return uniform(1 << 20, 4, 0), uniform(10_000_000, 4, 1)
     raise KeyError(name)
