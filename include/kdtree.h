@@ -82,7 +82,8 @@ typedef struct {
                         trips is handed to a second kernel in which a whole wave
                         finishes it (same results; keeps one far-off query from
                         holding the launch); -1 = never, 0 = default
-                        (KD_DEFAULT_HEAVY_TRIPS).  No hand-off happens when the
+                        (KD_DEFAULT_HEAVY_TRIPS, KD_DEFAULT_HEAVY_TRIPS_BOXES
+                        with subtree boxes).  No hand-off happens when the
                         per-query visited count is requested, which is the
                         single-lane traversal's by definition. */
     int prune;       /* pruning rule (results are identical under both):
@@ -98,6 +99,9 @@ typedef struct {
 } kd_opts;
 
 #define KD_DEFAULT_HEAVY_TRIPS 1024
+/* default trip budget when subtree boxes prune (opts.prune 0 or 2): the box
+ * test already shortens the long traversals the hand-off is for */
+#define KD_DEFAULT_HEAVY_TRIPS_BOXES 4096
 
 /* ------------------------------------------------------------ tree build */
 

@@ -257,6 +257,7 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     if (use.lds_levels < 0) use.lds_levels = 0;
     if (use.sort_bits < 0) use.sort_bits = 16;
     if (use.waves_per_cu == 0) use.waves_per_cu = p.K == 1 ? 32 : 24;  // measured best on 1M uniform
+    p.heavy_default = use.heavy_trips == 0;
     if (use.heavy_trips == 0) use.heavy_trips = KD_DEFAULT_HEAVY_TRIPS;
     if (use.heavy_trips < -1) return set_error(KD_EINVAL, "opts.heavy_trips must be -1, 0 or positive");
     if (use.block != 64 && use.block != 128 && use.block != 256 && use.block != 512 && use.block != 1024)

@@ -148,6 +148,7 @@ struct QueryPlan {
     int sort_bits = 32;
     int waves_per_cu = 8;
     int heavy_trips = 0;  // trip budget before the cooperative hand-off, 0 = none
+    bool heavy_default = true;  // the budget was left at its default
     int prune = 0;        // kd_opts.prune: 0 default, 1 split planes, 2 subtree boxes
 };
 int k_template(int k);

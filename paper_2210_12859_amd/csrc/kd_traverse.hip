@@ -1343,7 +1343,13 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     //          worst0  hand-off rows
     // The per-query visited count is the single-lane traversal's, so there
     // is no hand-off when it is requested.
-    const bool handoff = plan.heavy_trips > 0 && visited == nullptr;
+    // subtree boxes unless the paper's rule is asked for, explicitly or by
+    // requesting its processed-node count
+    const bool use_boxes = plan.prune == 2 || (plan.prune == 0 && visited == nullptr);
+    // trip budget: boxes shorten the long traversals, so their default is
+    // longer (gmm64-1m k = 8: 1.53 ms at 1024, 1.33 ms at 4096)
+    const int heavy_trips = plan.heavy_default && use_boxes ? KD_DEFAULT_HEAVY_TRIPS_BOXES : plan.heavy_trips;
+    const bool handoff = heavy_trips > 0 && visited == nullptr;
     const size_t cursor_bytes = size_t(MAX_GROUPS) * CURSOR_STRIDE * 4;  // 256 KB
     const size_t head = cursor_bytes + 4096;
     const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
@@ -1390,9 +1396,6 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
 
     TravArgs a = {};
     a.nodes = t->d_nodes;
-    // subtree boxes unless the paper's rule is asked for, explicitly or by
-    // requesting its processed-node count
-    const bool use_boxes = plan.prune == 2 || (plan.prune == 0 && visited == nullptr);
     a.boxes = use_boxes ? static_cast<const float*>(t->d_boxes) : nullptr;
     a.box_below = box_id_limit(t->N);
     a.refill_min = (use_boxes || plan.K == 1) ? 4u : 1u;  // measured best, see KD_REFILL_MIN_BATCHED
@@ -1422,7 +1425,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     const int coop_grid = dev.cus * 2;                      // workgroups of 4 waves
     const uint32_t heavy_cap = uint32_t(coop_grid) * 4u * KD_COOP_ROUNDS;  // rounds of one query per wave
     if (handoff) {
-        a.heavy_trips = uint32_t(plan.heavy_trips);
+        a.heavy_trips = uint32_t(heavy_trips);
         a.heavy_cap = heavy_cap;
         a.heavy_count = heavy_count;
         a.heavy_rows = heavy_rows;
