@@ -55,8 +55,11 @@ typedef enum {
  * next larger compiled list size, returning its first k entries (exact: the
  * k-best list is a prefix of any longer one). */
 #define KD_MAX_K 64
-/* Largest point count: child indices 2n+2 must fit in int32 (Sec. 3.2). */
-#define KD_MAX_POINTS (1LL << 30)
+/* Largest point count.  The traversal keeps 1-based node ids in int32: the
+ * children of id i are 2i and 2i + 1 (the level-order children 2n+1, 2n+2 of
+ * Sec. 3.2, shifted by one), so the largest id N and its child ids must stay
+ * below 2^31: N <= 2^30 - 1. */
+#define KD_MAX_POINTS ((1LL << 30) - 1)
 
 /* Launch tuning.  Every setting gives byte-identical results; only speed
  * differs.  Passing NULL means "the options kd_autotune chose for this tree

@@ -157,7 +157,7 @@ void pack_boxes(const float* pts, const int32_t* order, int64_t N, int D, std::v
 
 kd_status build_from_host(const float* hp, int64_t N, int dim, kd_tree* out) {
     if (!out) return set_error(KD_EINVAL, "kd_build: out is NULL");
-    if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build: N out of range [0, 2^30]");
+    if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build: N out of range [0, 2^30 - 1]");
     if (dim < 2 || dim > 4) return set_error(KD_EINVAL, "kd_build: dim must be 2, 3 or 4");
     if (N > 0 && !hp) return set_error(KD_EINVAL, "kd_build: points is NULL");
     for (int64_t i = 0; i < N * dim; ++i)
@@ -328,7 +328,7 @@ kd_status kd_build_host(const float* host_points, int64_t N, int dim, kd_tree* o
 
 kd_status kd_build(const float* points, int64_t N, int dim, kd_stream stream, kd_tree* out) {
     if (!out) return set_error(KD_EINVAL, "kd_build: out is NULL");
-    if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build: N out of range [0, 2^30]");
+    if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build: N out of range [0, 2^30 - 1]");
     if (dim < 2 || dim > 4) return set_error(KD_EINVAL, "kd_build: dim must be 2, 3 or 4");
     if (N > 0 && !points) return set_error(KD_EINVAL, "kd_build: points is NULL");
     try {
@@ -344,7 +344,7 @@ kd_status kd_build(const float* points, int64_t N, int dim, kd_stream stream, kd
 }
 
 kd_status kd_build_order_host(const float* host_points, int64_t N, int dim, int32_t* host_order) {
-    if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build_order_host: N out of range [0, 2^30]");
+    if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build_order_host: N out of range [0, 2^30 - 1]");
     if (dim < 1 || dim > 8) return set_error(KD_EINVAL, "kd_build_order_host: dim must be in 1..8");
     if (N > 0 && (!host_points || !host_order)) return set_error(KD_EINVAL, "kd_build_order_host: NULL pointer");
     try {

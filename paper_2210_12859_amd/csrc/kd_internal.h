@@ -71,7 +71,7 @@ inline int32_t box_id_limit(int64_t N) {
     int levels = 0;
     while (levels < 31 && (int64_t(1) << levels) <= N) ++levels;
     const int e = levels - KD_BOX_MIN_HEIGHT + 1;
-    return e <= 0 ? 1 : int32_t(1) << e;  // N <= 2^30: e <= 29
+    return e <= 0 ? 1 : int32_t(1) << e;  // N < 2^30: e <= 28
 }
 
 // Tuned launch parameters kept with a tree (filled by kd_autotune).

@@ -1356,7 +1356,6 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     const size_t sort_bytes = plan.sort_bits > 0 ? sort_scratch_bytes(Q, t->dim) : 0;
     const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
     const size_t learn_bytes = learned ? q4 : 0;
-    const size_t heavy_bytes = handoff ? q4 : 0;
     kd_status s = scratch(stream, query_scratch_bytes(Q, t->dim, plan.sort_bits > 0, learned != nullptr, handoff), &ws);
     if (s != KD_OK) return s;
     char* base = static_cast<char*>(ws);

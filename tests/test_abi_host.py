@@ -76,6 +76,14 @@ def test_build_validation():
     assert L.kd_build(pp, 4, 1, None, ctypes.byref(h)) == kd.KD_EINVAL
     assert L.kd_build(pp, -1, 3, None, ctypes.byref(h)) == kd.KD_EINVAL
     assert L.kd_build(pp, (1 << 30) + 1, 3, None, ctypes.byref(h)) == kd.KD_EINVAL
+    # N = 2^30: the largest 1-based node id would be 2^30, whose child ids
+    # 2^31 and 2^31 + 1 overflow int32; rejected before anything is read or
+    # allocated (the 4-point buffer is never touched)
+    for n in (1 << 30, (1 << 31) - 1):
+        assert L.kd_build(pp, n, 3, None, ctypes.byref(h)) == kd.KD_EINVAL
+        assert "2^30 - 1" in L.kd_last_error().decode()
+        assert L.kd_build_host(pp, n, 3, ctypes.byref(h)) == kd.KD_EINVAL
+        assert L.kd_build_order_host(pp, n, 3, None) == kd.KD_EINVAL
     assert L.kd_build(None, 4, 3, None, ctypes.byref(h)) == kd.KD_EINVAL
     assert L.kd_build(pp, 4, 3, None, None) == kd.KD_EINVAL
     bad = pts.copy()
