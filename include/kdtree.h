@@ -205,6 +205,15 @@ typedef struct {
 typedef struct {
     int64_t queries;       /* queries in the call */
     int64_t fallbacks;     /* queries re-run from R2 */
+    int64_t handed_off;    /* queries finished by the cooperative hand-off kernel */
+    int64_t visited;       /* nodes entered by the single-lane traversal, both runs
+                              of every query summed (nodes the hand-off kernel
+                              processes are not counted); equals the sum of the
+                              per-query visited counts when those are requested */
+    float sort_ms;         /* GPU time of each stage, from hipEvents on the */
+    float radius_ms;       /* stream: query reorder, initial radius (MLP), */
+    float traverse_ms;     /* traversal, hand-off kernel (0 when there is none) */
+    float handoff_ms;
 } kd_stats;
 
 /* Trains a radius model for k on the tree: labels are the k-th neighbour
@@ -218,7 +227,8 @@ kd_status kd_radius_model_train(kd_tree t, const float* train_q, int64_t Qt, int
 
 /* kd_knn with the model's initial radius (see above).  visited (nullable,
  * device uint32 [Q]) counts processed nodes of both runs; stats (nullable,
- * HOST) receives the fallback count, which synchronises the stream. */
+ * HOST) receives the counts and stage times above, which synchronises the
+ * stream. */
 kd_status kd_knn_learned(kd_tree t, kd_model m, const float* queries, int64_t Q, int k, float maxRadius,
                          int32_t* out_idx, float* out_d2, uint32_t* visited, kd_stats* stats, const kd_opts* opts,
                          kd_stream stream);
@@ -254,6 +264,24 @@ kd_status kd_model_free(kd_model m);
 kd_status kd_mlp_predict(kd_model m, const float* queries, int64_t n, float* y, kd_stream stream);
 kd_status kd_mlp_grad(kd_model m, const float* queries, const float* targets, int64_t n, float* host_grad,
                       float* host_loss, kd_stream stream);
+/* kd_mlp_worst0: the initial squared radius of the learned query path,
+ * worst0 = min(R2, fl32(r0 * r0)) with r0 = exp(y + margin) (R2 when r0 is
+ * not finite), R2 = fl32(maxRadius^2), for device queries [n][3], written to
+ * device float32 worst0[n] in the queries' order by the same kernel the
+ * learned query uses.  Synchronises the stream.
+ * kd_mlp_train_step: one step of the trainer on n device (query, target)
+ * rows: forward, backward, and one Adam update (betas 0.9, 0.999 and eps 1e-8
+ * as float32; bias corrections 1 - beta^step) of the model's float32
+ * parameters, which change in place -- not for a model that queries are
+ * using.  host_m, host_v (HOST float32 [4481], in/out) are Adam's moments;
+ * step >= 1 is Adam's step number; host_grad (HOST [4481], nullable)
+ * receives the gradient the update used, host_loss (nullable) the batch loss;
+ * kd_model_get_params returns the updated parameters.  n <= 2^20;
+ * synchronises the stream. */
+kd_status kd_mlp_worst0(kd_model m, const float* queries, int64_t n, float maxRadius, float* worst0,
+                        kd_stream stream);
+kd_status kd_mlp_train_step(kd_model m, const float* queries, const float* targets, int64_t n, int step, float lr,
+                            float* host_m, float* host_v, float* host_grad, float* host_loss, kd_stream stream);
 
 /* ---------------------------------------------------------------- batched */
 

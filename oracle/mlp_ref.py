@@ -141,6 +141,13 @@ def predict_worst0(theta, q, lo, inv, margin, R2) -> np.ndarray:
     """Initial squared search radius per query: min(R2, fl32(r0^2)) with
     r0 = exp(y + margin); a non-finite or negative r0 gives R2."""
     y, _ = forward(theta, normalize(q, lo, inv))
+    return worst0_from_y(y, margin, R2)
+
+
+def worst0_from_y(y, margin, R2) -> np.ndarray:
+    """The y -> worst0 step of predict_worst0: r0 = fl32(exp(y + margin)) in
+    float64, then min(R2, fl32(r0 * r0)); R2 when r0 is not finite."""
+    y = np.asarray(y, np.float64)
     with np.errstate(over="ignore"):
         r0 = fp32(np.exp(y + margin)).astype(np.float32)
     with np.errstate(over="ignore", invalid="ignore"):

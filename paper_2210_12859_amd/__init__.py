@@ -37,7 +37,9 @@ class KdTrainOpts(ctypes.Structure):
 
 
 class KdStats(ctypes.Structure):
-    _fields_ = [("queries", ctypes.c_int64), ("fallbacks", ctypes.c_int64)]
+    _fields_ = [("queries", ctypes.c_int64), ("fallbacks", ctypes.c_int64), ("handed_off", ctypes.c_int64),
+                ("visited", ctypes.c_int64), ("sort_ms", ctypes.c_float), ("radius_ms", ctypes.c_float),
+                ("traverse_ms", ctypes.c_float), ("handoff_ms", ctypes.c_float)]
 
 
 class KdJob(ctypes.Structure):
@@ -82,6 +84,8 @@ def lib():
         "kd_model_free": ([P], i32),
         "kd_mlp_predict": ([P, P, i64, P, P], i32),
         "kd_mlp_grad": ([P, P, P, i64, P, P, P], i32),
+        "kd_mlp_worst0": ([P, P, i64, f32, P, P], i32),
+        "kd_mlp_train_step": ([P, P, P, i64, i32, f32, P, P, P, P, P], i32),
         "kd_batch_create": ([P, i32, P, P, P], i32),
         "kd_batch_run": ([P, P], i32),
         "kd_batch_free": ([P], i32),
@@ -351,7 +355,7 @@ def kd_knn_learned(tree: Tree, model: Model, queries, k, max_radius=math.inf, ou
     _check(lib().kd_knn_learned(tree.handle, model.handle, _ptr(queries), queries.shape[0], int(k),
                                 float(max_radius), _ptr(out_idx), _ptr(out_d2), _ptr(visited),
                                 ctypes.byref(st) if st is not None else None, _opts(opts), _stream_handle(stream)))
-    stats = dict(queries=st.queries, fallbacks=st.fallbacks) if st is not None else None
+    stats = {name: getattr(st, name) for name, _ in KdStats._fields_} if st is not None else None
     return out_idx, out_d2, visited, stats
 
 
@@ -399,6 +403,38 @@ def kd_mlp_grad(model: Model, queries, targets, stream=None):
     loss = ctypes.c_float()
     _check(lib().kd_mlp_grad(model.handle, _ptr(queries), _ptr(targets), queries.shape[0],
                              g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss), _stream_handle(stream)))
+    return loss.value, g
+
+
+def kd_mlp_worst0(model: Model, queries, max_radius: float = math.inf, out=None, stream=None):
+    """Initial squared radius per query (device float32 [n], queries' order)."""
+    import torch
+    _require(queries, torch.float32, "queries")
+    if out is None:
+        out = torch.empty(queries.shape[0], dtype=torch.float32, device=queries.device)
+    _require(out, torch.float32, "out", (queries.shape[0],))
+    _check(lib().kd_mlp_worst0(model.handle, _ptr(queries), queries.shape[0], float(max_radius), _ptr(out),
+                               _stream_handle(stream)))
+    return out
+
+
+def kd_mlp_train_step(model: Model, queries, targets, step: int, lr: float, m, v, stream=None):
+    """One trainer step on the model (its parameters change in place).  m, v:
+    numpy float32 [4481] Adam moments, updated in place.  Returns (loss,
+    gradient as numpy float32 [4481])."""
+    import numpy as np
+    import torch
+    _require(queries, torch.float32, "queries")
+    _require(targets, torch.float32, "targets", (queries.shape[0],))
+    for name, a in (("m", m), ("v", v)):
+        if not (isinstance(a, np.ndarray) and a.dtype == np.float32 and a.shape == (MLP_NPARAM,)
+                and a.flags["C_CONTIGUOUS"]):
+            raise TypeError(f"{name} must be a contiguous numpy float32 array of {MLP_NPARAM}")
+    g = np.empty(MLP_NPARAM, np.float32)
+    loss = ctypes.c_float()
+    _check(lib().kd_mlp_train_step(model.handle, _ptr(queries), _ptr(targets), queries.shape[0], int(step),
+                                   float(lr), m.ctypes.data_as(ctypes.c_void_p), v.ctypes.data_as(ctypes.c_void_p),
+                                   g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss), _stream_handle(stream)))
     return loss.value, g
 
 

@@ -199,12 +199,17 @@ kd_status reorder_queries(kd_tree t, const float* queries, int64_t Q, int sort_b
                           uint32_t* zero, uint32_t nzero, hipStream_t st);
 kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan, int32_t* out_idx,
                   float* out_d2, uint32_t* visited, kd_stream stream, const LearnedSpec* learned = nullptr,
-                  uint32_t* fallbacks_out = nullptr);
+                  kd_stats* stats = nullptr);
 
 // ---- MLP kernels (kd_mlp.hip) ---------------------------------------------
 constexpr int MLP_NPARAM = 4481;
+// Adam hyper-parameters of the trainer (float32 values)
+constexpr float MLP_ADAM_BETA1 = 0.9f, MLP_ADAM_BETA2 = 0.999f, MLP_ADAM_EPS = 1e-8f;
 hipError_t launch_mlp_worst0(const float* P, const float* lo, const float* inv, float margin, float R2,
                              const void* sq, uint32_t Q, float* worst0, hipStream_t st);
+// worst0 for caller-layout queries [n][3], in caller order (recs: n x 16 bytes of scratch)
+hipError_t launch_mlp_worst0_rows(const float* P, const float* lo, const float* inv, float margin, float R2,
+                                  const float* queries, uint32_t n, void* recs, float* worst0, hipStream_t st);
 hipError_t launch_mlp_predict(const float* P, const float* lo, const float* inv, const float* qs, uint32_t n,
                               float* y, hipStream_t st);
 hipError_t launch_mlp_fwd_bwd(const float* P, const float* lo, const float* inv, const float* qs, const float* t,

@@ -26,6 +26,8 @@
 // every fragment is one 16-byte LDS read.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "kd_internal.h"
 
 namespace kd {
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(256) void mlp_worst0(const float* __restrict__ P, N
         const float y = mlp_tile(W, xs, lane);
         const uint32_t slot = tile * 64u + uint32_t(lane);
         if (slot < Q) {
-            const float r0 = __expf(y + margin);
+            const float r0 = expf(y + margin);
             float wv = R2;
             if (__builtin_isfinite(r0) && r0 >= 0.0f) {
                 const float r2 = r0 * r0;
@@ -506,12 +508,15 @@ __global__ __launch_bounds__(64) void mlp_fwd_bwd(const float* __restrict__ P, N
 }
 
 // Sum of the wave partials in a fixed order, then (step > 0) one Adam step on
-// the float32 master weights.  grad (nullable) receives the summed gradient;
-// loss (nullable, thread 0) the batch loss.
+// the float32 master weights.  bc1 = 1 - beta1^step and bc2 = 1 - beta2^step
+// come from the host (computed in double and rounded once: at small steps
+// 1 - beta2^step cancels, and a fast power would lose most of its digits).
+// grad (nullable) receives the summed gradient; loss (nullable, thread 0) the
+// batch loss.
 __global__ void mlp_reduce_adam(const float* __restrict__ part, const float* __restrict__ part_loss, int nparts,
                                 float inv_batch, float* __restrict__ P, float* __restrict__ m,
                                 float* __restrict__ v, int step, float lr, float beta1, float beta2, float eps,
-                                float* __restrict__ grad, float* __restrict__ loss) {
+                                float bc1, float bc2, float* __restrict__ grad, float* __restrict__ loss) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0 && loss) {
         float s = 0;
@@ -527,8 +532,6 @@ __global__ void mlp_reduce_adam(const float* __restrict__ part, const float* __r
         const float vv = beta2 * v[p] + (1.0f - beta2) * g * g;
         m[p] = mm;
         v[p] = vv;
-        const float bc1 = 1.0f - __powf(beta1, float(step));
-        const float bc2 = 1.0f - __powf(beta2, float(step));
         const float mhat = mm / bc1;
         const float vhat = vv / bc2;
         P[p] -= lr * mhat / (__fsqrt_rn(vhat) + eps);
@@ -541,7 +544,14 @@ __global__ void knn_label(const float* __restrict__ d2, int k, uint32_t n, float
     if (i >= n) return;
     float v = d2[size_t(i) * k + (k - 1)];
     v = v > 1e-14f ? v : 1e-14f;
-    t[i] = 0.5f * __logf(v);
+    t[i] = 0.5f * logf(v);
+}
+
+// Caller-layout queries [n][3] as traversal records (x, y, z, row = i).
+__global__ void caller_records3(const float* __restrict__ q, uint32_t n, float4* __restrict__ rec) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    rec[i] = make_float4(q[size_t(i) * 3 + 0], q[size_t(i) * 3 + 1], q[size_t(i) * 3 + 2], __uint_as_float(i));
 }
 
 Norm make_norm(const float* lo, const float* inv) {
@@ -572,6 +582,16 @@ hipError_t launch_mlp_worst0(const float* P, const float* lo, const float* inv, 
     return hipGetLastError();
 }
 
+hipError_t launch_mlp_worst0_rows(const float* P, const float* lo, const float* inv, float margin, float R2,
+                                  const float* queries, uint32_t n, void* recs, float* worst0, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(caller_records3, dim3((n + 255) / 256), dim3(256), 0, st, queries, n,
+                       static_cast<float4*>(recs));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_mlp_worst0(P, lo, inv, margin, R2, recs, n, worst0, st);
+}
+
 hipError_t launch_mlp_predict(const float* P, const float* lo, const float* inv, const float* qs, uint32_t n,
                               float* y, hipStream_t st) {
     if (n == 0) return hipSuccess;
@@ -589,8 +609,11 @@ hipError_t launch_mlp_fwd_bwd(const float* P, const float* lo, const float* inv,
 
 hipError_t launch_mlp_reduce_adam(const float* part, const float* part_loss, int nparts, uint32_t batch, float* P,
                                   float* m, float* v, int step, float lr, float* grad, float* loss, hipStream_t st) {
+    const float beta1 = MLP_ADAM_BETA1, beta2 = MLP_ADAM_BETA2;
+    const float bc1 = step > 0 ? float(1.0 - std::pow(double(beta1), double(step))) : 1.0f;
+    const float bc2 = step > 0 ? float(1.0 - std::pow(double(beta2), double(step))) : 1.0f;
     hipLaunchKernelGGL(mlp_reduce_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, part, part_loss, nparts,
-                       1.0f / float(batch), P, m, v, step, lr, 0.9f, 0.999f, 1e-8f, grad, loss);
+                       1.0f / float(batch), P, m, v, step, lr, beta1, beta2, MLP_ADAM_EPS, bc1, bc2, grad, loss);
     return hipGetLastError();
 }
 

@@ -300,7 +300,7 @@ kd_status kd_knn_learned(kd_tree t, kd_model m, const float* queries, int64_t Q,
     if (s != KD_OK) return s;
     if (!m) return set_error(KD_EINVAL, "kd_knn_learned: model is NULL");
     if (t->dim != 3) return set_error(KD_EUNSUPPORTED, "kd_knn_learned: the radius model is 3-D");
-    if (stats) *stats = kd_stats{0, 0};
+    if (stats) *stats = kd_stats{0, 0, 0, 0, 0.0f, 0.0f, 0.0f, 0.0f};
     if (Q == 0 || t->N == 0)
         return knn_entry(t, queries, Q, k, maxRadius, out_idx, out_d2, visited, opts, stream, "kd_knn_learned");
     QueryPlan plan;
@@ -311,13 +311,7 @@ kd_status kd_knn_learned(kd_tree t, kd_model m, const float* queries, int64_t Q,
     std::memcpy(ls.lo, m->lo, sizeof(ls.lo));
     std::memcpy(ls.inv, m->inv, sizeof(ls.inv));
     ls.margin = m->margin;
-    uint32_t fb = 0;
-    s = run_knn(t, queries, Q, plan, out_idx, out_d2, visited, stream, &ls, stats ? &fb : nullptr);
-    if (s == KD_OK && stats) {
-        stats->queries = Q;
-        stats->fallbacks = fb;
-    }
-    return s;
+    return run_knn(t, queries, Q, plan, out_idx, out_d2, visited, stream, &ls, stats);
 }
 
 kd_status kd_knn_with_radius(kd_tree t, const float* r0, const float* queries, int64_t Q, int k, float maxRadius,
@@ -375,6 +369,67 @@ kd_status kd_mlp_grad(kd_model m, const float* queries, const float* targets, in
         return KD_OK;
     } catch (const std::exception& e) {
         return set_error(KD_ENOMEM, std::string("kd_mlp_grad: ") + e.what());
+    }
+}
+
+kd_status kd_mlp_worst0(kd_model m, const float* queries, int64_t n, float maxRadius, float* worst0,
+                        kd_stream stream) {
+    if (!m) return set_error(KD_EINVAL, "kd_mlp_worst0: model is NULL");
+    if (n < 0 || n >= (int64_t(1) << 31)) return set_error(KD_EINVAL, "kd_mlp_worst0: n out of range");
+    if (std::isnan(maxRadius) || maxRadius < 0.0f)
+        return set_error(KD_EINVAL, "kd_mlp_worst0: maxRadius must be >= 0 (or +inf)");
+    if (n == 0) return KD_OK;
+    if (!queries || !worst0) return set_error(KD_EINVAL, "kd_mlp_worst0: NULL pointer");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const float R2 = maxRadius * maxRadius;
+    try {
+        DevBuf recs;
+        KD_HIP(recs.alloc(size_t(n) * 16));
+        KD_HIP(launch_mlp_worst0_rows(m->d_params, m->lo, m->inv, m->margin, R2, queries, uint32_t(n), recs.p, worst0,
+                                      st));
+        // the records are freed on return
+        KD_HIP(hipStreamSynchronize(st));
+        return KD_OK;
+    } catch (const std::exception& e) {
+        return set_error(KD_ENOMEM, std::string("kd_mlp_worst0: ") + e.what());
+    }
+}
+
+kd_status kd_mlp_train_step(kd_model m, const float* queries, const float* targets, int64_t n, int step, float lr,
+                            float* host_m, float* host_v, float* host_grad, float* host_loss, kd_stream stream) {
+    if (!m) return set_error(KD_EINVAL, "kd_mlp_train_step: model is NULL");
+    if (n < 1 || n > (1 << 20)) return set_error(KD_EINVAL, "kd_mlp_train_step: n out of range [1, 2^20]");
+    if (step < 1) return set_error(KD_EINVAL, "kd_mlp_train_step: step counts from 1");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return set_error(KD_EINVAL, "kd_mlp_train_step: lr must be > 0");
+    if (!queries || !targets || !host_m || !host_v) return set_error(KD_EINVAL, "kd_mlp_train_step: NULL pointer");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    try {
+        const int nparts = int((n + 63) / 64);
+        DevBuf part, part_loss, grad, loss, mom, vel;
+        KD_HIP(part.alloc(size_t(nparts) * MLP_NPARAM * sizeof(float)));
+        KD_HIP(part_loss.alloc(size_t(nparts) * sizeof(float)));
+        KD_HIP(grad.alloc(MLP_NPARAM * sizeof(float)));
+        KD_HIP(loss.alloc(sizeof(float)));
+        KD_HIP(mom.alloc(MLP_NPARAM * sizeof(float)));
+        KD_HIP(vel.alloc(MLP_NPARAM * sizeof(float)));
+        KD_HIP(hipMemcpyAsync(mom.p, host_m, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, st));
+        KD_HIP(hipMemcpyAsync(vel.p, host_v, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, st));
+        KD_HIP(launch_mlp_fwd_bwd(m->d_params, m->lo, m->inv, queries, targets, nullptr, 0, uint32_t(n),
+                                  part.as<float>(), part_loss.as<float>(), st));
+        KD_HIP(launch_mlp_reduce_adam(part.as<float>(), part_loss.as<float>(), nparts, uint32_t(n), m->d_params,
+                                      mom.as<float>(), vel.as<float>(), step, lr, grad.as<float>(), loss.as<float>(),
+                                      st));
+        KD_HIP(hipMemcpyAsync(host_m, mom.p, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, st));
+        KD_HIP(hipMemcpyAsync(host_v, vel.p, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, st));
+        if (host_grad) KD_HIP(hipMemcpyAsync(host_grad, grad.p, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, st));
+        float hl = 0;
+        KD_HIP(hipMemcpyAsync(&hl, loss.p, sizeof(float), hipMemcpyDeviceToHost, st));
+        KD_HIP(hipMemcpyAsync(m->params.data(), m->d_params, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, st));
+        KD_HIP(hipStreamSynchronize(st));
+        if (host_loss) *host_loss = hl;
+        return KD_OK;
+    } catch (const std::exception& e) {
+        return set_error(KD_ENOMEM, std::string("kd_mlp_train_step: ") + e.what());
     }
 }
 

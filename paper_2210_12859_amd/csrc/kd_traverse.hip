@@ -78,6 +78,7 @@ struct TravArgs {
     // learned-radius kernels
     const float* worst0;     // [Q] initial squared radius per slot
     uint32_t* fb_count;      // queries restarted from R2 (nullable)
+    unsigned long long* vis_total;  // entered nodes summed over the launch (nullable, learned kernels)
     uint8_t* fb_flag;        // [Q] caller order, 1 = restarted from R2 (nullable)
     // hand-off of long traversals to the cooperative kernel
     uint32_t heavy_trips;    // trip budget per query, 0 = none
@@ -639,6 +640,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
     Lane<D, K> s;
     s.curr = 0;
     uint32_t restarts = 0;  // learned runs restarted from R2 by this lane
+    uint32_t vis_sum = 0;   // entered nodes of this lane's finished and handed-off queries (learned)
     for (;;) {
         const uint64_t need = wave_ballot(s.curr == 0);
         if (need && !ws.exhausted && uint32_t(__popcll(need)) >= a.refill_min) {
@@ -702,6 +704,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                 if (pos < a.heavy_cap) {
                     a.heavy_rows[pos] = s.row;
                     if (LEARNED && a.fb_flag) a.fb_flag[s.row] = s.fell_back ? 1 : 2;
+                    if (LEARNED) vis_sum += s.vis;
                     s.curr = 0;
                     handed = true;
                 }
@@ -712,6 +715,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                     ++restarts;
                     lane_reset<D, K>(s, a.k, a.R2);
                 } else {
+                    if (LEARNED) vis_sum += s.vis;
                     lane_finish<D, K, LEARNED>(s, a);
                 }
             }
@@ -719,9 +723,14 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
     }
     if (LEARNED && a.fb_count) {
         // one atomic per wave (all lanes are here: the loop exit is uniform)
+        uint64_t vs = vis_sum;
 #pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) restarts += __shfl_xor(restarts, m);
+        for (int m = 32; m >= 1; m >>= 1) {
+            restarts += __shfl_xor(restarts, m);
+            vs += uint64_t(__shfl_xor(uint32_t(vs), m)) | (uint64_t(__shfl_xor(uint32_t(vs >> 32), m)) << 32);
+        }
         if (lane == 0 && restarts) atomicAdd(a.fb_count, restarts);
+        if (lane == 0 && a.vis_total && vs) atomicAdd(a.vis_total, (unsigned long long)vs);
     }
 }
 
@@ -1333,9 +1342,25 @@ size_t query_scratch_bytes(int64_t Q, int dim, bool sorted, bool learned, bool h
     return head + sq_bytes + sort_bytes + (learned ? q4 : 0) + (handoff ? q4 : 0);
 }
 
+namespace {
+// Five events bracketing the stages of one query call (sort, initial radius,
+// traversal, hand-off), destroyed with the call.
+struct StageEvents {
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    kd_status create() {
+        for (auto& e : ev) KD_HIP(hipEventCreate(&e));
+        return KD_OK;
+    }
+    ~StageEvents() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace
+
 kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan, int32_t* out_idx,
                   float* out_d2, uint32_t* visited, kd_stream stream, const LearnedSpec* learned,
-                  uint32_t* fallbacks_out) {
+                  kd_stats* stats) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const DeviceInfo& dev = device_info(t->device);
     void* ws = nullptr;
@@ -1362,12 +1387,23 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     uint32_t* counter1 = reinterpret_cast<uint32_t*>(base);
     uint32_t* fb_count = reinterpret_cast<uint32_t*>(base + cursor_bytes);
     uint32_t* heavy_count = reinterpret_cast<uint32_t*>(base + cursor_bytes + 4);
+    unsigned long long* vis_total = reinterpret_cast<unsigned long long*>(base + cursor_bytes + 8);
     void* sq = base + head;
     void* sort_ws = base + head + sq_bytes;
     float* worst0 = learned ? reinterpret_cast<float*>(base + head + sq_bytes + sort_bytes) : nullptr;
     int32_t* heavy_rows = handoff ? reinterpret_cast<int32_t*>(base + head + sq_bytes + sort_bytes + learn_bytes)
                                   : nullptr;
-    const uint32_t n_counters = uint32_t(cursor_bytes / 4) + 2;  // range cursors, restart count, hand-off count
+    // range cursors, restart count, hand-off count, entered-node total (64-bit)
+    const uint32_t n_counters = uint32_t(cursor_bytes / 4) + 4;
+
+    // stage events for the caller's stats (stage times need a synchronisation,
+    // which stats implies)
+    StageEvents sev;
+    if (stats) {
+        s = sev.create();
+        if (s != KD_OK) return s;
+        KD_HIP(hipEventRecord(sev.ev[0], st));
+    }
 
     // query reorder: Morton sort whose last pass writes the traversal records
     hipEvent_t evs;
@@ -1378,6 +1414,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     if (s != KD_OK) return s;
     s = timing_end(st, evs, "sort");
     if (s != KD_OK) return s;
+    if (stats) KD_HIP(hipEventRecord(sev.ev[1], st));
 
     if (learned) {
         hipEvent_t evm;
@@ -1392,6 +1429,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
         s = timing_end(st, evm, "mlp");
         if (s != KD_OK) return s;
     }
+    if (stats) KD_HIP(hipEventRecord(sev.ev[2], st));
 
     TravArgs a = {};
     a.nodes = t->d_nodes;
@@ -1420,6 +1458,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
         a.worst0 = worst0;
         a.fb_count = fb_count;
         a.fb_flag = learned->fb_flag;
+        a.vis_total = vis_total;
     }
     const int coop_grid = dev.cus * 2;                      // workgroups of 4 waves
     const uint32_t heavy_cap = uint32_t(coop_grid) * 4u * KD_COOP_ROUNDS;  // rounds of one query per wave
@@ -1452,6 +1491,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     if (e != hipSuccess) return hip_error(e, "knn_persistent launch");
     s = timing_end(st, ev0, "traverse");
     if (s != KD_OK) return s;
+    if (stats) KD_HIP(hipEventRecord(sev.ev[3], st));
     if (handoff) {
         // queries over the trip budget, one wave each (the count is read on
         // the device; waves beyond it exit at once)
@@ -1479,9 +1519,17 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
         s = timing_end(st, evc, "coop");
         if (s != KD_OK) return s;
     }
-    if (fallbacks_out) {
-        KD_HIP(hipMemcpyAsync(fallbacks_out, fb_count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    if (stats) {
+        KD_HIP(hipEventRecord(sev.ev[4], st));
+        uint32_t cnt[4] = {0, 0, 0, 0};  // restarts, hand-offs, entered nodes (lo, hi)
+        KD_HIP(hipMemcpyAsync(cnt, fb_count, sizeof(cnt), hipMemcpyDeviceToHost, st));
         KD_HIP(hipStreamSynchronize(st));
+        stats->queries = Q;
+        stats->fallbacks = cnt[0];
+        stats->handed_off = handoff ? std::min(cnt[1], heavy_cap) : 0;
+        stats->visited = learned ? int64_t(uint64_t(cnt[2]) | (uint64_t(cnt[3]) << 32)) : -1;
+        float* ms[4] = {&stats->sort_ms, &stats->radius_ms, &stats->traverse_ms, &stats->handoff_ms};
+        for (int i = 0; i < 4; ++i) KD_HIP(hipEventElapsedTime(ms[i], sev.ev[i], sev.ev[i + 1]));
     }
     return KD_OK;
 }
