@@ -179,6 +179,27 @@ kd_status kd_knn_ex(kd_tree t, const float* queries, int64_t Q, int k, float max
 #define KD_WS_LEARNED 1
 kd_status kd_workspace_size(int64_t Q, int k, int flags, size_t* bytes);
 
+/* kd_knn for callers that cannot allocate device memory: code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, validation, kernels and results as kd_knn (default launch
+ * options, or the ones kd_autotune kept for the tree), but the call's scratch
+ * comes from one fixed device array of KD_NOALLOC_SCRATCH_BYTES that the
+ * library's code object holds on every device it runs on, from module load
+ * until the process ends; the call itself allocates nothing and creates no
+ * events (kd_timing_enable does not apply to it).  The caller still provides
+ * queries and outputs.
+ *   Capacity: the scratch a call needs is kd_workspace_size's per-dim figure;
+ *   64 MiB holds Q <= 1,104,800 queries for dim 2 and 3 and Q <= 616,042 for
+ *   dim 4.  A larger Q fails with KD_EINVAL before anything is enqueued.
+ *   The tree must live on the current device (else KD_EINVAL).
+ *   Every call on a device shares that device's array, which keeps the last
+ *   call's contents (the call clears its own counters on the stream before
+ *   use): calls that overlap in time on one device race and give undefined
+ *   results, so issue them on one stream or order them with events. */
+#define KD_NOALLOC_SCRATCH_BYTES (64u << 20)
+kd_status kd_knn_noalloc(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius,
+                         int32_t* out_idx, float* out_d2, kd_stream stream);
+
 /* ------------------------------------------------- learned initial radius */
 
 /* A small MLP (3 -> 64 -> 64 -> 1, ReLU; bfloat16 operands, float32

@@ -73,6 +73,7 @@ def lib():
         "kd_fcp": ([P, P, i64, f32, P, P, P], i32),
         "kd_knn": ([P, P, i64, i32, f32, P, P, P], i32),
         "kd_knn_ex": ([P, P, i64, i32, f32, P, P, P, P, P], i32),
+        "kd_knn_noalloc": ([P, P, i64, i32, f32, P, P, P], i32),
         "kd_radius_model_train": ([P, P, i64, i32, P, P, P], i32),
         "kd_knn_learned": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
         "kd_knn_with_radius": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
@@ -248,6 +249,19 @@ def kd_knn(tree: Tree, queries, k, max_radius=math.inf, out_idx=None, out_d2=Non
     out_idx, out_d2 = _outputs(queries, k, out_idx, out_d2, want_d2)
     _check(lib().kd_knn(tree.handle, _ptr(queries), queries.shape[0], int(k), float(max_radius),
                         _ptr(out_idx), _ptr(out_d2), _stream_handle(stream)))
+    return out_idx, out_d2
+
+
+def kd_knn_noalloc(tree: Tree, queries, k, max_radius=math.inf, out_idx=None, out_d2=None, want_d2=True,
+                   stream=None):
+    """kd_knn through the entry point that allocates no device memory (its
+    scratch is a fixed library array; output tensors allocated here when not
+    given)."""
+    import torch
+    _require(queries, torch.float32, "queries")
+    out_idx, out_d2 = _outputs(queries, k, out_idx, out_d2, want_d2)
+    _check(lib().kd_knn_noalloc(tree.handle, _ptr(queries), queries.shape[0], int(k), float(max_radius),
+                                _ptr(out_idx), _ptr(out_d2), _stream_handle(stream)))
     return out_idx, out_d2
 
 

@@ -35,6 +35,7 @@ SOURCES = [
     ("kd_model.cpp", True, []),
     ("kd_batch.cpp", True, []),
     ("kd_autotune.cpp", True, []),
+    ("kd_noalloc.hip", True, []),
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",

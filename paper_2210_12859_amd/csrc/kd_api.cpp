@@ -290,7 +290,8 @@ kd_status check_query_args_public(kd_tree t, const float* queries, int64_t Q, in
 }
 
 kd_status knn_entry(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius, int32_t* out_idx,
-                    float* out_d2, uint32_t* visited, const kd_opts* opts, kd_stream stream, const char* fn) {
+                    float* out_d2, uint32_t* visited, const kd_opts* opts, kd_stream stream, const char* fn,
+                    const FixedScratch* fixed) {
     kd_status s = check_query_args(t, queries, Q, k, maxRadius, out_idx, fn);
     if (s != KD_OK) return s;
     QueryPlan plan;
@@ -309,7 +310,7 @@ kd_status knn_entry(kd_tree t, const float* queries, int64_t Q, int k, float max
         }
         return KD_OK;
     }
-    return run_knn(t, queries, Q, plan, out_idx, out_d2, visited, stream);
+    return run_knn(t, queries, Q, plan, out_idx, out_d2, visited, stream, nullptr, nullptr, fixed);
 }
 
 }  // namespace kd

@@ -16,10 +16,6 @@
 
 namespace kd {
 
-kd_status resolve_plan_public(kd_tree t, int k, float maxRadius, const kd_opts* o, QueryPlan& p);
-kd_status knn_entry(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius, int32_t* out_idx,
-                    float* out_d2, uint32_t* visited, const kd_opts* opts, kd_stream stream, const char* fn);
-
 bool tuned_opts(kd_tree t, int K, kd_opts* out) {
     std::lock_guard<std::mutex> lk(t->tune_mu);
     for (const auto& e : t->tuned)

@@ -59,8 +59,6 @@ void free_batch(kd_batch b) {
 
 }  // namespace
 
-kd_status resolve_plan_public(kd_tree t, int k, float maxRadius, const kd_opts* o, QueryPlan& p);
-
 }  // namespace kd
 
 using namespace kd;

@@ -197,9 +197,27 @@ size_t query_scratch_bytes(int64_t Q, int dim, bool sorted, bool learned, bool h
 // zero[0..nzero) on the way.  ws holds sort_scratch_bytes(Q, dim) when sort_bits > 0.
 kd_status reorder_queries(kd_tree t, const float* queries, int64_t Q, int sort_bits, void* ws, void* sq,
                           uint32_t* zero, uint32_t nzero, hipStream_t st);
+// A caller-provided device scratch region of `bytes` bytes that replaces the
+// per-stream buffer; a call whose scratch does not fit fails with KD_EINVAL
+// before any launch.  Calls given one records no timing events.
+struct FixedScratch {
+    void* ptr;
+    size_t bytes;
+};
 kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan, int32_t* out_idx,
                   float* out_d2, uint32_t* visited, kd_stream stream, const LearnedSpec* learned = nullptr,
-                  kd_stats* stats = nullptr);
+                  kd_stats* stats = nullptr, const FixedScratch* fixed = nullptr);
+
+// ---- query entry helpers (kd_api.cpp) --------------------------------------
+// Validation shared by the query entry points (nothing enqueued on error).
+kd_status check_query_args_public(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius,
+                                  const int32_t* out_idx, const char* fn);
+// Launch plan for (tree, k) from opts, else the tree's tuned options, else defaults.
+kd_status resolve_plan_public(kd_tree t, int k, float maxRadius, const kd_opts* o, QueryPlan& p);
+// Validated plain kNN: empty trees answered without traversal, else run_knn.
+kd_status knn_entry(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius, int32_t* out_idx,
+                    float* out_d2, uint32_t* visited, const kd_opts* opts, kd_stream stream, const char* fn,
+                    const FixedScratch* fixed = nullptr);
 
 // ---- MLP kernels (kd_mlp.hip) ---------------------------------------------
 constexpr int MLP_NPARAM = 4481;

@@ -73,12 +73,6 @@ kd_status upload_params(kd_model m) {
 
 }  // namespace
 
-kd_status knn_entry(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius, int32_t* out_idx,
-                    float* out_d2, uint32_t* visited, const kd_opts* opts, kd_stream stream, const char* fn);
-kd_status resolve_plan_public(kd_tree t, int k, float maxRadius, const kd_opts* o, QueryPlan& p);
-kd_status check_query_args_public(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius,
-                                  const int32_t* out_idx, const char* fn);
-
 }  // namespace kd
 
 using namespace kd;

@@ -1360,7 +1360,7 @@ struct StageEvents {
 
 kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan, int32_t* out_idx,
                   float* out_d2, uint32_t* visited, kd_stream stream, const LearnedSpec* learned,
-                  kd_stats* stats) {
+                  kd_stats* stats, const FixedScratch* fixed) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const DeviceInfo& dev = device_info(t->device);
     void* ws = nullptr;
@@ -1381,8 +1381,23 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     const size_t sort_bytes = plan.sort_bits > 0 ? sort_scratch_bytes(Q, t->dim) : 0;
     const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
     const size_t learn_bytes = learned ? q4 : 0;
-    kd_status s = scratch(stream, query_scratch_bytes(Q, t->dim, plan.sort_bits > 0, learned != nullptr, handoff), &ws);
-    if (s != KD_OK) return s;
+    const size_t ws_bytes = query_scratch_bytes(Q, t->dim, plan.sort_bits > 0, learned != nullptr, handoff);
+    kd_status s = KD_OK;
+    if (fixed) {
+        if (ws_bytes > fixed->bytes)
+            return set_error(KD_EINVAL, "query scratch of " + std::to_string(ws_bytes) +
+                                            " bytes exceeds the fixed scratch of " + std::to_string(fixed->bytes) +
+                                            " bytes (too many queries for this entry point)");
+        ws = fixed->ptr;
+    } else {
+        s = scratch(stream, ws_bytes, &ws);
+        if (s != KD_OK) return s;
+    }
+    // timing events only for calls that may create them
+    auto tbegin = [&](hipEvent_t* ev) -> kd_status {
+        *ev = nullptr;
+        return fixed ? KD_OK : timing_begin(st, ev);
+    };
     char* base = static_cast<char*>(ws);
     uint32_t* counter1 = reinterpret_cast<uint32_t*>(base);
     uint32_t* fb_count = reinterpret_cast<uint32_t*>(base + cursor_bytes);
@@ -1407,7 +1422,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
 
     // query reorder: Morton sort whose last pass writes the traversal records
     hipEvent_t evs;
-    s = timing_begin(st, &evs);
+    s = tbegin(&evs);
     if (s != KD_OK) return s;
     hipError_t e = hipSuccess;
     s = reorder_queries(t, queries, Q, plan.sort_bits, sort_ws, sq, counter1, n_counters, st);
@@ -1418,7 +1433,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
 
     if (learned) {
         hipEvent_t evm;
-        s = timing_begin(st, &evm);
+        s = tbegin(&evm);
         if (s != KD_OK) return s;
         if (learned->params)
             e = launch_mlp_worst0(learned->params, learned->lo, learned->inv, learned->margin, plan.R2, sq,
@@ -1485,7 +1500,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     if (grid > 8 && grid % 8) grid -= grid % 8;
     if (grid < 1) grid = 1;
     hipEvent_t ev0;
-    s = timing_begin(st, &ev0);
+    s = tbegin(&ev0);
     if (s != KD_OK) return s;
     e = dispatch_dk(t->dim, plan.K, a, learned != nullptr, block, int(grid), lds_bytes, st);
     if (e != hipSuccess) return hip_error(e, "knn_persistent launch");
@@ -1512,7 +1527,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
         c.heavy_cap = heavy_cap;
         c.heavy_rows = heavy_rows;
         hipEvent_t evc;
-        s = timing_begin(st, &evc);
+        s = tbegin(&evc);
         if (s != KD_OK) return s;
         e = launch_coop(t->dim, plan.K, c, coop_grid, st);
         if (e != hipSuccess) return hip_error(e, "knn_coop launch");
