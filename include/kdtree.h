@@ -82,7 +82,8 @@ typedef struct {
     int waves_per_cu;/* persistent grid size in waves per compute unit (capped by
                         occupancy); 0 = default (32 for fcp / k = 1, else 24) */
     int heavy_trips; /* a query still unfinished after this many traversal loop
-                        trips is handed to a second kernel in which a whole wave
+                        trips (checked every 16th trip of its wave, so up to 15
+                        more) is handed to a second kernel in which a whole wave
                         finishes it (same results; keeps one far-off query from
                         holding the launch); -1 = never, 0 = default
                         (KD_DEFAULT_HEAVY_TRIPS, KD_DEFAULT_HEAVY_TRIPS_BOXES

@@ -299,7 +299,7 @@ struct Lane {
     int32_t curr, prev;
     int32_t row;
     uint32_t vis;
-    uint32_t trips;    // loop trips spent on the current query
+    uint32_t t0;       // the wave's trip count when the current query started
     float w0;          // initial squared radius of the current run
     bool fell_back;    // the learned run found < k points and was restarted
     bool far_entry;    // the last step moved into a far child
@@ -319,12 +319,13 @@ __device__ __forceinline__ void lane_reset(Lane<D, K>& s, int k, float w0) {
 }
 
 template <int D, int K, bool LEARNED>
-__device__ __forceinline__ void lane_start(Lane<D, K>& s, const TravArgs& a, const NodeRec<D>& qr, float w0) {
+__device__ __forceinline__ void lane_start(Lane<D, K>& s, const TravArgs& a, const NodeRec<D>& qr, float w0,
+                                           uint32_t wtrip = 0) {
 #pragma unroll
     for (int j = 0; j < D; ++j) s.q[j] = qr.c[j];
     s.row = qr.idx;
     s.vis = 0;
-    s.trips = 0;
+    s.t0 = wtrip;
     s.fell_back = false;
     lane_reset<D, K>(s, a.k, LEARNED ? w0 : a.R2);
 }
@@ -379,7 +380,7 @@ __device__ __forceinline__ void lane_finish(const Lane<D, K>& s, const TravArgs&
 // is the caller-index array when records hold no index): the state-machine
 // step at curr, then up to F fused "return to parent" steps.  Returns the new
 // curr (0 = traversal finished).
-template <int D, int K, int F, bool CAP = false>
+template <int D, int K, int F, bool CAP = false, bool FAR = true>
 __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D], int32_t idx,
                                              const int32_t* __restrict__ ids,
                                              const float (&anc)[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1],
@@ -395,8 +396,9 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     // skip: the caller found the subtree out of range on entry; it is left
     // at once, as if coming back from it
     const bool enter = from_parent & !skip;
-    if (from_parent) ++s.vis;  // entered nodes
+    if (from_parent & skip) ++s.vis;  // entered nodes: this one is left at once
     if (enter) {
+        ++s.vis;
         // processNode on the first visit: exact binary32 squared distance,
         // left to right, and insertion into the k-best list
         float d2 = dx[0] * dx[0];
@@ -468,7 +470,7 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
     }
     s.prev = nprev;
     s.curr = next;
-    s.far_entry = far_next;
+    if (FAR) s.far_entry = far_next;  // read by box tests only
     return next;
 }
 
@@ -641,6 +643,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
     s.curr = 0;
     uint32_t restarts = 0;  // learned runs restarted from R2 by this lane
     uint32_t vis_sum = 0;   // entered nodes of this lane's finished and handed-off queries (learned)
+    uint32_t wtrip = 0;     // trips of this wave (wave-uniform)
     for (;;) {
         const uint64_t need = wave_ballot(s.curr == 0);
         if (need && !ws.exhausted && uint32_t(__popcll(need)) >= a.refill_min) {
@@ -652,7 +655,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                 const NodeRec<D> v = shfl_rec<D>(chunk, src);
                 const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
                 if (s.curr == 0 && rank < take1) {
-                    lane_start<D, K, LEARNED>(s, a, v, vw);
+                    lane_start<D, K, LEARNED>(s, a, v, vw, wtrip);
                 }
             }
             cpos += take1;
@@ -671,7 +674,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                     const NodeRec<D> v = shfl_rec<D>(chunk, src);
                     const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
                     if (s.curr == 0 && rank >= take1 && r2 < take2) {
-                        lane_start<D, K, LEARNED>(s, a, v, vw);
+                        lane_start<D, K, LEARNED>(s, a, v, vw, wtrip);
                     }
                     cpos = take2;
                 } else {
@@ -681,6 +684,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
             }
         }
         if (!wave_any(s.curr != 0)) break;
+        ++wtrip;
         if (s.curr != 0) {
             float c[D];
             int32_t idx;
@@ -694,12 +698,15 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                 if (s.far_entry && s.curr < a.box_below)
                     skip = box_d2<D>(a.boxes, s.curr, s.q) > key_d2(s.L[K - 1]);
             }
-            const int32_t next = lane_step<D, K, F>(s, c, idx, ids, anc, a.N, 0.0f, 0, skip);
+            const int32_t next = lane_step<D, K, F, false, BOX>(s, c, idx, ids, anc, a.N, 0.0f, 0, skip);
             bool handed = false;
-            if (++s.trips == a.heavy_trips && next != 0) {
+            // every running lane steps once per wave trip, so a query's trip
+            // count is the wave's count since it started; the budget is
+            // checked every 16th wave trip (a scalar test), once per query
+            if (a.heavy_trips && (wtrip & 15u) == 0 && next != 0 && wtrip - s.t0 - a.heavy_trips < 16u) {
                 // over budget: the cooperative kernel finishes this query,
                 // unless it already holds heavy_cap queries (then the lane
-                // goes on; the budget is checked once per query)
+                // goes on)
                 const uint32_t pos = atomicAdd(a.heavy_count, 1u);
                 if (pos < a.heavy_cap) {
                     a.heavy_rows[pos] = s.row;
