@@ -1,0 +1,162 @@
+"""Full-size GPU parity for every configuration the benchmark times or the
+design notes quote, in the exact launch configuration that is timed, against
+the oracle (the ordered recursion of Sec. 3.1 over the oracle's own tree, or
+the brute-force definition on sampled rows).
+
+Bar: indices byte-identical and squared distances bit-identical, row by row.
+
+* uniform-1m (the headline): the timed call (paper's pruning rule, no
+  per-query counts, so the cooperative hand-off is active) and the library
+  default (subtree boxes), k = 1, 8, 64, every row;
+* gmm64-1m: the library default, k = 1, 8, every row;
+* clustered-10m, k = 16: a fixed 1M-query subset (rows 0 .. 2^20 - 1) under
+  the paper's rule, the library default and the learned radius;
+* shells-100m, k = 32, maxRadius 0.005: 2,000 sampled rows against brute
+  force, and the learned radius byte-identical to the plain call on every row;
+* 4-D uniform, 1M points x 10M queries (the shape of the paper's Table 1):
+  kNN k = 8 and fcp, rows 0 .. 2^20 - 1."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2210_12859_amd as kd  # noqa: E402
+from paper_2210_12859_amd import datagen  # noqa: E402
+
+PLAIN = {"prune": 1}  # the timed headline call
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return torch.device("cuda:0")
+
+
+def _same(gi, gd, oi, od, ctx):
+    gi = np.asarray(gi).reshape(oi.shape)
+    gd = np.asarray(gd).reshape(od.shape)
+    bad = np.nonzero((gi != oi).any(axis=1))[0] if oi.ndim == 2 else np.nonzero(gi != oi)[0]
+    assert len(bad) == 0, f"{ctx}: {len(bad)} rows differ, first {bad[:5]}"
+    assert np.array_equal(gd.view(np.uint32), od.view(np.uint32)), f"{ctx}: d2 bits differ"
+
+
+@pytest.fixture(scope="module")
+def uniform_1m(oracle_lib):
+    P, Qs = datagen.workload("uniform-1m")
+    order = oracle_lib.build_tree(P)
+    tree = kd.kd_build(torch.from_numpy(P).to(_dev()))
+    yield P, Qs, order, tree, torch.from_numpy(Qs).to(_dev())
+    tree.close()
+
+
+@pytest.mark.parametrize("k", [1, 8, 64])
+def test_uniform_1m_timed_call_every_row(oracle_lib, uniform_1m, k):
+    P, Qs, order, tree, q = uniform_1m
+    print(f"[gpu] uniform-1m k={k}: timed call and library default", flush=True)
+    ai, ad, _ = kd.kd_knn_ex(tree, q, k, opts=PLAIN)
+    bi, bd = kd.kd_knn(tree, q, k)
+    torch.cuda.synchronize()
+    oi, od, _ = oracle_lib.knn(P, order, Qs, k)
+    _same(ai.cpu().numpy(), ad.cpu().numpy(), oi, od, f"uniform-1m k={k} paper rule")
+    _same(bi.cpu().numpy(), bd.cpu().numpy(), oi, od, f"uniform-1m k={k} default")
+
+
+def test_gmm64_1m_default_every_row(oracle_lib):
+    P, Qs = datagen.workload("gmm64-1m")
+    order = oracle_lib.build_tree(P)
+    tree = kd.kd_build(torch.from_numpy(P).to(_dev()))
+    q = torch.from_numpy(Qs).to(_dev())
+    for k in (1, 8):
+        print(f"[gpu] gmm64-1m k={k}: library default", flush=True)
+        gi, gd = kd.kd_knn(tree, q, k)
+        torch.cuda.synchronize()
+        oi, od, _ = oracle_lib.knn(P, order, Qs, k)
+        _same(gi.cpu().numpy(), gd.cpu().numpy(), oi, od, f"gmm64-1m k={k}")
+    tree.close()
+
+
+def test_clustered_10m_subset_three_rules(oracle_lib):
+    P, Qs = datagen.workload("clustered-10m")
+    k, n = 16, 1 << 20
+    print("[gpu] clustered-10m: GPU build and queries", flush=True)
+    tree = kd.kd_build(torch.from_numpy(P).to(_dev()))
+    q = torch.from_numpy(Qs[:n]).to(_dev())
+    pi, pd, _ = kd.kd_knn_ex(tree, q, k, opts=PLAIN)
+    bi, bd = kd.kd_knn(tree, q, k)
+    train = torch.from_numpy(datagen.training_queries("clustered-10m", 1 << 20, 7)).to(_dev())
+    model = kd.kd_radius_model_train(tree, train, k, epochs=4, batch=8192, seed=0)
+    li, ld, _, _ = kd.kd_knn_learned(tree, model, q, k)
+    torch.cuda.synchronize()
+    print("[gpu] clustered-10m: oracle tree and traversal of the subset", flush=True)
+    order = oracle_lib.build_tree(P)
+    oi, od, _ = oracle_lib.knn(P, order, Qs[:n], k)
+    _same(pi.cpu().numpy(), pd.cpu().numpy(), oi, od, "clustered-10m paper rule")
+    _same(bi.cpu().numpy(), bd.cpu().numpy(), oi, od, "clustered-10m default")
+    _same(li.cpu().numpy(), ld.cpu().numpy(), oi, od, "clustered-10m learned")
+    model.close()
+    tree.close()
+
+
+def _slab_brute(oracle_lib, P, xs_order, xs_sorted, q, k, maxr):
+    """The brute-force definition over the points whose x lies within maxr
+    (plus a relative margin) of the query's: every point with d2 <= fl(maxr^2)
+    is among them, since d2 >= fl(dx^2) for the x offset alone.  Candidates
+    keep their caller order, so ties still go to the smaller index."""
+    r = float(maxr) * (1.0 + 1e-5) + 1e-12
+    lo = np.searchsorted(xs_sorted, q[0] - r, side="left")
+    hi = np.searchsorted(xs_sorted, q[0] + r, side="right")
+    cand = np.sort(xs_order[lo:hi])
+    if len(cand) == 0:
+        return np.full(k, -1, np.int32), np.full(k, np.inf, np.float32)
+    bi, bd = oracle_lib.brute(P[cand], q[None, :], k, maxr)
+    bi = bi[0]
+    return np.where(bi >= 0, cand[np.maximum(bi, 0)], -1).astype(np.int32), bd[0]
+
+
+def test_shells_100m_sampled_and_learned_every_row(oracle_lib):
+    n, k, maxr = 100_000_000, 32, 0.005
+    print("[gpu] shells-100m: generating", flush=True)
+    P = datagen.shells(n, seed=0)
+    Qs = datagen.shells(n, seed=1)
+    print("[gpu] shells-100m: build and plain query", flush=True)
+    tree = kd.kd_build(torch.from_numpy(P).to(_dev()))
+    q = torch.from_numpy(Qs).to(_dev())
+    gi, gd = kd.kd_knn(tree, q, k, maxr)
+    print("[gpu] shells-100m: learned query", flush=True)
+    train = torch.from_numpy(datagen.training_queries("shells-100m", 1 << 20, 7)).to(_dev())
+    model = kd.kd_radius_model_train(tree, train, k, epochs=4, batch=8192, seed=0)
+    li, ld, _, st = kd.kd_knn_learned(tree, model, q, k, maxr, want_stats=True)
+    torch.cuda.synchronize()
+    assert torch.equal(li, gi), "learned indices differ from plain"
+    assert torch.equal(ld.view(torch.int32), gd.view(torch.int32)), "learned d2 differ from plain"
+    del li, ld
+    model.close()
+    rows = np.random.default_rng(0).choice(n, 2000, replace=False)
+    r = torch.from_numpy(rows).to(_dev())
+    gi_s, gd_s = gi[r].cpu().numpy(), gd[r].cpu().numpy()
+    print("[gpu] shells-100m: brute force of 2000 sampled rows", flush=True)
+    xs_order = np.argsort(P[:, 0], kind="stable").astype(np.int64)
+    xs_sorted = P[xs_order, 0].astype(np.float64)
+    for t, row in enumerate(rows):
+        bi, bd = _slab_brute(oracle_lib, P, xs_order, xs_sorted, Qs[row], k, maxr)
+        assert np.array_equal(gi_s[t], bi), f"row {row}"
+        assert np.array_equal(gd_s[t].view(np.uint32), bd.view(np.uint32)), f"row {row}"
+    tree.close()
+
+
+def test_uniform4d_1m_q10m_subset(oracle_lib):
+    P, Qs = datagen.workload("uniform4d-1m-q10m")
+    n = 1 << 20
+    tree = kd.kd_build(torch.from_numpy(P).to(_dev()))
+    q = torch.from_numpy(Qs).to(_dev())
+    print("[gpu] uniform4d-1m-q10m: kNN k=8 and fcp over 10M queries", flush=True)
+    gi, gd = kd.kd_knn(tree, q, 8)
+    fi, fd = kd.kd_fcp(tree, q)
+    torch.cuda.synchronize()
+    order = oracle_lib.build_tree(P)
+    oi, od, _ = oracle_lib.knn(P, order, Qs[:n], 8)
+    _same(gi[:n].cpu().numpy(), gd[:n].cpu().numpy(), oi, od, "4-D k=8")
+    _same(fi[:n].cpu().numpy(), fd[:n].cpu().numpy(), oi[:, 0], od[:, 0], "4-D fcp")
+    tree.close()
