@@ -72,19 +72,41 @@ def load_traffic(kernel_key: str, cur_hash: str, launches_units: float):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(P, Qs, k, reps=2):
-    import numpy as np
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(P, Qs, k, reps=3, single_sample=1 << 18):
+    """The oracle (plain recursive traversal, C, one thread per host core
+    with dynamic chunks) on the workload's queries, best of reps; plus the
+    same on one thread over the first single_sample queries."""
     import oracle
     order = oracle.build_tree(P)  # untimed
     threads = oracle.default_threads()
-    best = math.inf
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        oracle.knn(P, order, Qs, k, nthreads=threads)
-        best = min(best, time.perf_counter() - t0)
-    return dict(value=Qs.shape[0] / best, unit="queries/s", cores=threads, kind="oracle",
+
+    def best_of(qs, nthreads):
+        best = math.inf
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.knn(P, order, qs, k, nthreads=nthreads)
+            best = min(best, time.perf_counter() - t0)
+        return qs.shape[0] / best
+
+    value = best_of(Qs, threads)
+    one = best_of(Qs[:single_sample], 1)
+    return dict(value=value, unit="queries/s", cores=threads, kind="oracle",
                 sample=f"all {Qs.shape[0]} queries of the workload, k={k}, recursive traversal, "
-                       f"best of {reps}, tree built untimed")
+                       f"best of {reps}, tree built untimed",
+                value_1_core=one, sample_1_core=f"first {min(single_sample, Qs.shape[0])} queries, 1 thread, "
+                                                f"best of {reps}",
+                cpu_model=host_cpu_model(), host_threads=os.cpu_count())
 
 
 def copy_calibration(nbytes=1 << 30, reps=3):
@@ -188,11 +210,14 @@ def bench_learned(kd, datagen, tree, q, oi, od, k, args, plain_visited, plain_ms
 
 
 def bench_batched(kd, datagen, args):
-    """Many trees in one captured launch pipeline: jobs drawn like the batched
-    workload (N log-uniform, D in {2,3,4}, uniform or GMM-64, k in {1,8,32},
-    Q = N), trees built untimed.  Timed: kd_batch_run (hipGraph replay of the
-    whole pipeline) per step, against the same jobs as one kd_knn call each.
-    Results are checked identical."""
+    """Many trees in one captured launch pipeline: the batched workload (512
+    trees, N log-uniform [1K, 2M], D in {2,3,4}, uniform or GMM-64, k in
+    {1,8,32}, Q = N), trees built untimed.  Timed: kd_batch_run (hipGraph
+    replay of the whole pipeline) per step with the default options, then
+    after the batch autotuner (untimed) picked options per (dim, k) group,
+    against the same jobs as one kd_knn call each.  Results are checked
+    identical.  Roofline: node bytes of the entered nodes (the default rule's
+    count, summed over the jobs) per replay of the whole pipeline."""
     import torch
     dev = torch.device("cuda:0")
     jobs_meta = datagen.batched_jobs(args.batch_jobs, seed=42, n_max=args.batch_nmax)
@@ -210,6 +235,12 @@ def bench_batched(kd, datagen, args):
     torch.cuda.synchronize()
     log(f"batched: {len(jobs)} trees built in {time.perf_counter() - t0:.1f}s (untimed)")
     total_q = sum(j["queries"].shape[0] for j in jobs)
+    # entered nodes under the default rule (the batch's), node bytes summed
+    alg_bytes = 0
+    for j in jobs:
+        _, _, v = kd.kd_knn_ex(j["tree"], j["queries"], j["k"], want_d2=False, want_visited=True,
+                               opts={"prune": 2})
+        alg_bytes += int(v.to(torch.int64).sum().item()) * j["queries"].shape[1] * 4
     batch = kd.Batch(jobs)
     stream = torch.cuda.current_stream()
 
@@ -230,18 +261,29 @@ def bench_batched(kd, datagen, args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    ms_d = timed(lambda: batch.run(stream), args.steps)
+    t0 = time.perf_counter()
+    tuned = batch.autotune(reps=2, stream=stream)
+    tune_s = time.perf_counter() - t0
     ms_b = timed(lambda: batch.run(stream), args.steps)
     ms_s = timed(run_single, max(1, args.steps // 4))
     identical = all(torch.equal(j["out_idx"], oi) and torch.equal(j["out_d2"].view(torch.int32), od.view(torch.int32))
                     for j, (oi, od) in zip(jobs, single))
+    groups = batch.info()
     batch.close()
     for j in jobs:
         j["tree"].close()
-    log(f"batched: {ms_b:.3f} ms/step ({total_q / ms_b / 1e3:.1f} M queries/s), one call per tree "
-        f"{ms_s:.3f} ms/step, identical {identical}")
+    achieved = alg_bytes / (ms_b / 1e3) / 1e9
+    log(f"batched: default {ms_d:.3f} ms/step, tuned {ms_b:.3f} ms/step ({total_q / ms_b / 1e3:.1f} M queries/s), "
+        f"one call per tree {ms_s:.3f} ms/step, identical {identical}")
     return {"value": total_q / (ms_b / 1e3), "unit": "queries/s", "ms_per_step": ms_b, "jobs": len(jobs),
-            "total_queries": total_q, "ms_per_step_one_call_per_tree": ms_s, "speedup_vs_one_call_per_tree": ms_s / ms_b,
+            "total_queries": total_q, "ms_per_step_default_options": ms_d, "autotune_s": tune_s,
+            "tuned_options": [dict(dim=g[0], K=g[1], queries=g[2], **o) for g, o in zip(groups, tuned)],
+            "ms_per_step_one_call_per_tree": ms_s, "speedup_vs_one_call_per_tree": ms_s / ms_b,
             "identical_to_single_calls": identical,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBPS, "alg_bytes_per_replay": alg_bytes,
+                         "timed": "whole graph replay (sort, gather, traversal, hand-off of every group)"},
             "sample": f"{len(jobs)} trees, N log-uniform [1000, {args.batch_nmax}], D in {{2,3,4}}, uniform or "
                       f"GMM-64, k in {{1,8,32}}, Q = N, seed 42; hipGraph replay per step"}
 
@@ -259,8 +301,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-radius variant")
     ap.add_argument("--no-boxes", action="store_true", help="skip the default (bounding-box) pruning variant")
     ap.add_argument("--train-epochs", type=int, default=8)
-    ap.add_argument("--batch-jobs", type=int, default=128, help="trees in the batched measurement (0 = skip)")
-    ap.add_argument("--batch-nmax", type=int, default=262144, help="largest tree of the batched measurement")
+    ap.add_argument("--batch-jobs", type=int, default=512, help="trees in the batched measurement (0 = skip)")
+    ap.add_argument("--batch-nmax", type=int, default=2000000, help="largest tree of the batched measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()

@@ -310,8 +310,13 @@ kd_status kd_mlp_train_step(kd_model m, const float* queries, const float* targe
 /* Many independent trees and query sets in one call.  Jobs are grouped by
  * (dimension, list size); each group runs as ONE persistent traversal launch
  * in which every lane carries its own tree, after a Morton sort of the
- * group's queries (each job along its own tree's curve).  Per job, results
- * are exactly those of kd_knn on that job. */
+ * group's queries (each job along its own tree's curve).  Queries still
+ * unfinished after the trip budget (opts.heavy_trips) are finished by the
+ * cooperative kernel, one wave each, as in kd_knn.  3-D jobs with a radius
+ * model (the job's own, else the call's) start from the model's initial
+ * radius and restart from R2 when it held fewer than k points, as in
+ * kd_knn_learned.  Per job, results are exactly those of kd_knn on that job,
+ * whatever the model and the options. */
 typedef struct {
     kd_tree tree;
     const float* queries;  /* device [Q][dim] */
@@ -320,22 +325,41 @@ typedef struct {
     float maxRadius;
     int32_t* out_idx;      /* device [Q][k] */
     float* out_d2;         /* device [Q][k] or NULL */
+    kd_model model;        /* radius model for this job (3-D trees), or NULL */
 } kd_job;
 
 typedef struct kd_batch_s* kd_batch;
 
 /* Validates the jobs, allocates the batch's scratch (owned by the batch) and
  * captures the whole pipeline into a hipGraph (on a private stream when
- * stream is NULL).  The job pointers are baked into the graph: they must stay
- * valid for the batch's lifetime.  opts (nullable): block, waves_per_cu,
- * sort_bits and prune apply to every group. */
-kd_status kd_batch_create(const kd_job* jobs, int n_jobs, const kd_opts* opts, kd_stream stream, kd_batch* out);
+ * stream is NULL).  The job pointers and models are baked into the graph:
+ * they must stay valid for the batch's lifetime.
+ *   model : nullable; the radius model of 3-D jobs whose kd_job.model is NULL.
+ *   opts  : nullable; block, waves_per_cu, sort_bits, heavy_trips and prune
+ *           apply to every group (waves_per_cu 0: 32 for k = 1, else 24;
+ *           sort_bits -1: 16 Morton bits below the group's job-index bits,
+ *           rounded up to whole bytes). */
+kd_status kd_batch_create(const kd_job* jobs, int n_jobs, kd_model model, const kd_opts* opts, kd_stream stream,
+                          kd_batch* out);
 /* Replays the captured graph on stream (asynchronous). */
 kd_status kd_batch_run(kd_batch b, kd_stream stream);
 /* Frees the batch; the caller must have synchronised every stream it ran on. */
 kd_status kd_batch_free(kd_batch b);
 /* create + run + synchronise + free. */
-kd_status kd_knn_batched(const kd_job* jobs, int n_jobs, const kd_opts* opts, kd_stream stream);
+kd_status kd_knn_batched(const kd_job* jobs, int n_jobs, kd_model model, const kd_opts* opts, kd_stream stream);
+/* Autotuner of the batched pipeline: for each (dimension, list size) group,
+ * runs the group's pipeline with each candidate launch option (workgroup size
+ * 256 / 512 x waves per CU 16 / 24 / 32 x sort key bits 16 / 24 / 32), reps
+ * timed runs each, checks that every candidate writes the same outputs (a
+ * 64-bit checksum of the group's result rows; a difference is KD_EHIP), keeps
+ * the fastest per group and captures the graph again.  Overwrites the jobs'
+ * outputs (with the same results).  class_opts (HOST, nullable, n_classes
+ * entries on input) receives the options kept per group, in kd_batch_info's
+ * order; *n_classes (nullable) the number of groups.  Synchronises. */
+kd_status kd_batch_autotune(kd_batch b, int reps, kd_stream stream, kd_opts* class_opts, int* n_classes);
+/* The groups of a batch (HOST arrays of cap entries, each nullable):
+ * dimension, compiled list size, query count. */
+kd_status kd_batch_info(kd_batch b, int* n_classes, int* class_dim, int* class_k, int64_t* class_queries, int cap);
 
 /* --------------------------------------------------------------- autotune */
 

@@ -45,7 +45,7 @@ class KdStats(ctypes.Structure):
 class KdJob(ctypes.Structure):
     _fields_ = [("tree", ctypes.c_void_p), ("queries", ctypes.c_void_p), ("Q", ctypes.c_int64),
                 ("k", ctypes.c_int), ("maxRadius", ctypes.c_float), ("out_idx", ctypes.c_void_p),
-                ("out_d2", ctypes.c_void_p)]
+                ("out_d2", ctypes.c_void_p), ("model", ctypes.c_void_p)]
 
 
 class KdOpts(ctypes.Structure):
@@ -87,10 +87,12 @@ def lib():
         "kd_mlp_grad": ([P, P, P, i64, P, P, P], i32),
         "kd_mlp_worst0": ([P, P, i64, f32, P, P], i32),
         "kd_mlp_train_step": ([P, P, P, i64, i32, f32, P, P, P, P, P], i32),
-        "kd_batch_create": ([P, i32, P, P, P], i32),
+        "kd_batch_create": ([P, i32, P, P, P, P], i32),
         "kd_batch_run": ([P, P], i32),
         "kd_batch_free": ([P], i32),
-        "kd_knn_batched": ([P, i32, P, P], i32),
+        "kd_knn_batched": ([P, i32, P, P, P], i32),
+        "kd_batch_autotune": ([P, i32, P, P, P], i32),
+        "kd_batch_info": ([P, P, P, P, P, i32], i32),
         "kd_autotune": ([P, P, i64, i32, f32, P, P, P], i32),
         "kd_tree_get_tuned": ([P, i32, P], i32),
         "kd_tree_set_tuned": ([P, i32, P], i32),
@@ -453,7 +455,7 @@ def kd_mlp_train_step(model: Model, queries, targets, step: int, lr: float, m, v
 
 
 def _job_array(jobs):
-    """jobs: list of dicts {tree, queries, k, max_radius=inf, out_idx, out_d2=None}."""
+    """jobs: list of dicts {tree, queries, k, max_radius=inf, out_idx, out_d2=None, model=None}."""
     import torch
     arr = (KdJob * max(1, len(jobs)))()
     for i, j in enumerate(jobs):
@@ -467,23 +469,43 @@ def _job_array(jobs):
             _require(d2, torch.float32, f"jobs[{i}].out_d2")
             if d2.numel() != q.shape[0] * j["k"]:
                 raise ValueError(f"jobs[{i}].out_d2 must hold Q*k entries")
+        m = j.get("model")
         arr[i] = KdJob(j["tree"].handle, q.data_ptr(), q.shape[0], int(j["k"]), float(j.get("max_radius", math.inf)),
-                       j["out_idx"].data_ptr(), d2.data_ptr() if d2 is not None else None)
+                       j["out_idx"].data_ptr(), d2.data_ptr() if d2 is not None else None,
+                       m.handle if m is not None else None)
     return arr
 
 
 class Batch:
     """A captured batched pipeline (kd_batch); run() replays its hipGraph."""
 
-    def __init__(self, jobs, opts=None, stream=None):
-        self._jobs = jobs  # keep the tensors alive
+    def __init__(self, jobs, opts=None, model=None, stream=None):
+        self._jobs = jobs  # keep the tensors (and models) alive
+        self._model = model
         arr = _job_array(jobs)
         h = ctypes.c_void_p()
-        _check(lib().kd_batch_create(arr, len(jobs), _opts(opts), _stream_handle(stream), ctypes.byref(h)))
+        _check(lib().kd_batch_create(arr, len(jobs), model.handle if model is not None else None, _opts(opts),
+                                     _stream_handle(stream), ctypes.byref(h)))
         self._h = h
 
     def run(self, stream=None):
         _check(lib().kd_batch_run(self._h, _stream_handle(stream)))
+
+    def info(self):
+        """[(dim, list size, queries)] of the batch's (dimension, list size) groups."""
+        n = ctypes.c_int()
+        cap = 64
+        dims, ks, qs = (ctypes.c_int * cap)(), (ctypes.c_int * cap)(), (ctypes.c_int64 * cap)()
+        _check(lib().kd_batch_info(self._h, ctypes.byref(n), dims, ks, qs, cap))
+        return [(dims[i], ks[i], qs[i]) for i in range(min(n.value, cap))]
+
+    def autotune(self, reps=3, stream=None):
+        """Times launch options per group, keeps the fastest; returns their options."""
+        cap = 64
+        arr = (KdOpts * cap)()
+        n = ctypes.c_int(cap)
+        _check(lib().kd_batch_autotune(self._h, int(reps), _stream_handle(stream), arr, ctypes.byref(n)))
+        return [_opts_dict(arr[i]) for i in range(min(n.value, cap))]
 
     def close(self):
         if self._h:
@@ -497,9 +519,10 @@ class Batch:
             pass
 
 
-def kd_knn_batched(jobs, opts=None, stream=None):
+def kd_knn_batched(jobs, opts=None, model=None, stream=None):
     arr = _job_array(jobs)
-    _check(lib().kd_knn_batched(arr, len(jobs), _opts(opts), _stream_handle(stream)))
+    _check(lib().kd_knn_batched(arr, len(jobs), model.handle if model is not None else None, _opts(opts),
+                                _stream_handle(stream)))
 
 
 def _opts_dict(o: KdOpts):

@@ -4,11 +4,16 @@
 // jobs' queries form one slot space; the class pipeline is a Morton sort of
 // the whole space (job index in the top bits, so every job stays contiguous
 // and is sorted along its own tree's Z-order curve), a gather into 32-byte
-// query records, and ONE persistent traversal launch whose lanes each carry
-// their own tree.  kd_batch_create captures the pipelines of all classes into
-// a hipGraph once; kd_batch_run replays it.
+// query records, the initial radii of the jobs that have a radius model (3-D),
+// ONE persistent traversal launch whose lanes each carry their own tree, and
+// the cooperative kernel for the queries that ran over the trip budget.
+// kd_batch_create captures the pipelines of all classes into a hipGraph once;
+// kd_batch_run replays it; kd_batch_autotune times launch options per class
+// and captures the graph again with the fastest.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -24,7 +29,12 @@ struct kd_batch_s {
         uint32_t n = 0;
         int njobs = 0;
         kd::BatchJob* d_jobs = nullptr;
-        void* ws = nullptr;          // sort scratch, records, cursors
+        std::vector<kd::BatchJob> jobs;  // host copy (output pointers for the autotuner's checksum)
+        void* ws = nullptr;              // sort scratch | records | counters | hand-off rows | initial radii
+        kd::MlpJob* d_mlp = nullptr;     // radius-model table of the class's jobs with a model
+        int n_mlp = 0;
+        uint32_t mlp_tiles = 0;
+        kd::QueryPlan plan;
     };
     std::vector<Class> classes;
     std::vector<std::pair<int32_t*, float*>> empty_out;  // jobs over empty trees
@@ -32,6 +42,7 @@ struct kd_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t total_queries = 0;
+    int device = 0;
 };
 
 namespace kd {
@@ -46,6 +57,29 @@ __global__ void batch_fill_empty(int32_t* idx, float* d2, int64_t n) {
     }
 }
 
+// Order-independent, position-sensitive 64-bit checksum of one job's outputs,
+// folded into *h (the autotuner checks that every candidate gives the same).
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+__global__ void output_checksum(const int32_t* idx, const float* d2, int64_t n, uint64_t salt,
+                                unsigned long long* h) {
+    uint64_t acc = 0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const uint64_t v = uint64_t(uint32_t(idx[i])) | (d2 ? uint64_t(__float_as_uint(d2[i])) << 32 : 0);
+        acc ^= mix64(v ^ mix64(uint64_t(i) ^ salt));
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        acc ^= uint64_t(uint32_t(__shfl_xor(uint32_t(acc), m))) |
+               (uint64_t(uint32_t(__shfl_xor(uint32_t(acc >> 32), m))) << 32);
+    if ((threadIdx.x & 63) == 0 && acc) atomicXor(h, (unsigned long long)acc);
+}
+
 void free_batch(kd_batch b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -53,8 +87,115 @@ void free_batch(kd_batch b) {
     for (auto& c : b->classes) {
         if (c.d_jobs) (void)hipFree(c.d_jobs);
         if (c.ws) (void)hipFree(c.ws);
+        if (c.d_mlp) (void)hipFree(c.d_mlp);
     }
     delete b;
+}
+
+struct ClassLayout {
+    size_t sort_b, rec_b, cur_b, heavy_b, w0_b;
+};
+
+ClassLayout class_layout(const kd_batch_s::Class& c, int device) {
+    ClassLayout L;
+    L.sort_b = (batch_sort_scratch_bytes(c.n) + 255) & ~size_t(255);
+    L.rec_b = (size_t(c.n) * batch_rec_bytes() + 255) & ~size_t(255);
+    L.cur_b = (batch_cursor_bytes() + 255) & ~size_t(255);
+    L.heavy_b = (size_t(batch_heavy_cap(device)) * 8 + 255) & ~size_t(255);
+    L.w0_b = c.n_mlp ? (size_t(c.n) * 4 + 255) & ~size_t(255) : 0;
+    return L;
+}
+
+// The whole pipeline of one class on stream st.
+kd_status enqueue_class(const kd_batch_s::Class& c, int device, hipStream_t st) {
+    const ClassLayout L = class_layout(c, device);
+    char* ws = static_cast<char*>(c.ws);
+    const uint32_t* perm = nullptr;
+    kd_status s = batch_sort(c.d_jobs, c.njobs, c.dim, c.n, c.plan.sort_bits, ws, st, &perm);
+    if (s != KD_OK) return s;
+    char* recs = ws + L.sort_b;
+    uint32_t* counters = reinterpret_cast<uint32_t*>(recs + L.rec_b);
+    int32_t* heavy = reinterpret_cast<int32_t*>(recs + L.rec_b + L.cur_b);
+    BatchLearned bl{c.d_mlp, c.n_mlp, c.mlp_tiles,
+                    c.n_mlp ? reinterpret_cast<float*>(recs + L.rec_b + L.cur_b + L.heavy_b) : nullptr};
+    return run_batch_class(c.d_jobs, c.njobs, c.dim, c.K, c.n, perm, recs, counters, c.plan, device, st,
+                           c.n_mlp ? &bl : nullptr, heavy);
+}
+
+// Captures every class into one graph: one graph branch per (dim, K) class
+// (the classes are independent, so their persistent launches overlap and the
+// long traversals that end one class run beside the next class's work).
+// Branch streams use the default priority; they fork from and join back into
+// the capture stream, which is a private one when the caller passes the
+// default stream (that stream cannot be captured).
+kd_status capture_batch(kd_batch b, hipStream_t cs_in) {
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    hipStream_t cs = cs_in;
+    hipStream_t own = nullptr;
+    if (!cs) {
+        KD_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        cs = own;
+    }
+    std::vector<hipStream_t> side(b->classes.size(), nullptr);
+    std::vector<hipEvent_t> done(b->classes.size(), nullptr);
+    hipEvent_t fork = nullptr;
+    auto release = [&]() {
+        for (hipStream_t x : side)
+            if (x) (void)hipStreamDestroy(x);
+        for (hipEvent_t x : done)
+            if (x) (void)hipEventDestroy(x);
+        if (fork) (void)hipEventDestroy(fork);
+        if (own) (void)hipStreamDestroy(own);
+    };
+    hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    for (size_t i = 0; i < side.size() && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        release();
+        return hip_error(e, "kd_batch: branch streams");
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        release();
+        return hip_error(e, "kd_batch: begin capture");
+    }
+    for (size_t i = 0; i < b->empty_out.size(); ++i) {
+        const int64_t n = b->empty_n[i];
+        hipLaunchKernelGGL(batch_fill_empty, dim3(unsigned((n + 255) / 256)), dim3(256), 0, cs,
+                           b->empty_out[i].first, b->empty_out[i].second, n);
+    }
+    kd_status s = KD_OK;
+    e = hipEventRecord(fork, cs);
+    for (size_t i = 0; i < b->classes.size() && s == KD_OK && e == hipSuccess; ++i) {
+        e = hipStreamWaitEvent(side[i], fork, 0);
+        if (e != hipSuccess) break;
+        s = enqueue_class(b->classes[i], b->device, side[i]);
+        if (s != KD_OK) break;
+        e = hipEventRecord(done[i], side[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[i], 0);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    release();
+    if (s == KD_OK && e != hipSuccess) s = hip_error(e, "kd_batch: branch capture");
+    if (s == KD_OK && ec != hipSuccess) s = hip_error(ec, "kd_batch: end capture");
+    if (s != KD_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    b->graph = graph;
+    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_error(e, "kd_batch: instantiate");
+    return KD_OK;
 }
 
 }  // namespace
@@ -65,7 +206,8 @@ using namespace kd;
 
 extern "C" {
 
-kd_status kd_batch_create(const kd_job* jobs, int n_jobs, const kd_opts* opts, kd_stream stream, kd_batch* out) {
+kd_status kd_batch_create(const kd_job* jobs, int n_jobs, kd_model model, const kd_opts* opts, kd_stream stream,
+                          kd_batch* out) {
     if (!out) return set_error(KD_EINVAL, "kd_batch_create: out is NULL");
     if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return set_error(KD_EINVAL, "kd_batch_create: bad job list");
     // validate every job before allocating anything
@@ -78,18 +220,18 @@ kd_status kd_batch_create(const kd_job* jobs, int n_jobs, const kd_opts* opts, k
         if (std::isnan(J.maxRadius) || J.maxRadius < 0.0f) return set_error(KD_EINVAL, f + ": bad maxRadius");
         if (J.Q > 0 && (!J.queries || !J.out_idx)) return set_error(KD_EINVAL, f + ": NULL pointer");
     }
-    QueryPlan plan;
-    kd_status s = KD_OK;
-    if (n_jobs > 0) {
-        s = resolve_plan_public(jobs[0].tree, 1, INFINITY, opts, plan);
-        if (s != KD_OK) return s;
-    }
+    // options shared by every class; the list size of each class sets its
+    // default persistent grid
+    QueryPlan base;
+    kd_status s = resolve_plan_public(nullptr, 1, INFINITY, opts, base);
+    if (s != KD_OK) return s;
     std::unique_ptr<kd_batch_s, void (*)(kd_batch)> b(new kd_batch_s, free_batch);
-    int device = 0;
-    KD_HIP(hipGetDevice(&device));
+    KD_HIP(hipGetDevice(&b->device));
 
-    // group by (dim, K); host job tables with class slot bases
+    // group by (dim, K); host job tables with class slot bases, and the
+    // radius-model table of the 3-D jobs with a model
     std::map<std::pair<int, int>, std::vector<BatchJob>> groups;
+    std::map<std::pair<int, int>, std::vector<MlpJob>> mlp;
     for (int i = 0; i < n_jobs; ++i) {
         const kd_job& J = jobs[i];
         b->total_queries += J.Q;
@@ -100,16 +242,16 @@ kd_status kd_batch_create(const kd_job* jobs, int n_jobs, const kd_opts* opts, k
             continue;
         }
         const int K = k_template(J.k);
-        auto& g = groups[{J.tree->dim, K}];
+        const int D = J.tree->dim;
+        auto& g = groups[{D, K}];
         BatchJob bj{};
         bj.nodes = J.tree->d_nodes;
         // subtree boxes unless the paper's rule alone is asked for
-        bj.boxes = plan.prune == 1 ? nullptr : static_cast<const float*>(J.tree->d_boxes);
+        bj.boxes = base.prune == 1 ? nullptr : static_cast<const float*>(J.tree->d_boxes);
         bj.box_below = box_id_limit(J.tree->N);
         bj.queries = J.queries;
         bj.out_idx = J.out_idx;
         bj.out_d2 = J.out_d2;
-        const int D = J.tree->dim;
         const int bits = D == 2 ? 16 : (D == 3 ? 10 : 8);
         for (int d = 0; d < 4; ++d) {
             const float ext = J.tree->hi[d] - J.tree->lo[d];
@@ -120,12 +262,26 @@ kd_status kd_batch_create(const kd_job* jobs, int n_jobs, const kd_opts* opts, k
         bj.k = J.k;
         const float r = J.maxRadius;
         bj.R2 = r * r;
-        uint64_t base = g.empty() ? 0 : uint64_t(g.back().slot_base) + g.back().Q;
-        if (base + uint64_t(J.Q) >= (uint64_t(1) << 31))
+        uint64_t start = g.empty() ? 0 : uint64_t(g.back().slot_base) + g.back().Q;
+        if (start + uint64_t(J.Q) >= (uint64_t(1) << 31))
             return set_error(KD_EINVAL, "kd_batch_create: more than 2^31 queries in one (dim, k) class");
-        bj.slot_base = uint32_t(base);
+        bj.slot_base = uint32_t(start);
         bj.Q = uint32_t(J.Q);
         bj.vec_store = 0;
+        const kd_model m = J.model ? J.model : model;
+        bj.learned = 0;
+        if (m && D == 3) {
+            MlpJob mj{};
+            s = model_view(m, &mj);
+            if (s != KD_OK) return s;
+            auto& mt = mlp[{D, K}];
+            mj.R2 = bj.R2;
+            mj.slot_base = bj.slot_base;
+            mj.Q = bj.Q;
+            mj.tile_base = mt.empty() ? 0 : mt.back().tile_base + (mt.back().Q + 63) / 64;
+            mt.push_back(mj);
+            bj.learned = 1;
+        }
         g.push_back(bj);
     }
     for (auto& kv : groups) {
@@ -134,94 +290,33 @@ kd_status kd_batch_create(const kd_job* jobs, int n_jobs, const kd_opts* opts, k
         c.K = kv.first.second;
         c.njobs = int(kv.second.size());
         c.n = kv.second.back().slot_base + kv.second.back().Q;
-        KD_HIP(hipMalloc(&c.d_jobs, kv.second.size() * sizeof(BatchJob)));
+        c.jobs = kv.second;
+        c.plan = base;
+        c.plan.K = c.K;
+        if (!opts || opts->waves_per_cu == 0) c.plan.waves_per_cu = c.K == 1 ? 32 : 24;
+        if (!opts || opts->sort_bits < 0) {
+            // the job index takes the top bits of the sort key: keep 16 bits
+            // of Morton code below it
+            int jb = 0;
+            while ((1 << jb) < c.njobs) ++jb;
+            c.plan.sort_bits = std::min(32, ((jb + 16 + 7) / 8) * 8);
+        }
         b->classes.push_back(c);  // owned (freed on error) from here on
-        KD_HIP(hipMemcpy(b->classes.back().d_jobs, kv.second.data(), kv.second.size() * sizeof(BatchJob),
-                         hipMemcpyHostToDevice));
-        const size_t sort_b = (batch_sort_scratch_bytes(c.n) + 255) & ~size_t(255);
-        const size_t rec_b = (size_t(c.n) * batch_rec_bytes() + 255) & ~size_t(255);
-        KD_HIP(hipMalloc(&b->classes.back().ws, sort_b + rec_b + batch_cursor_bytes()));
+        kd_batch_s::Class& cc = b->classes.back();
+        KD_HIP(hipMalloc(&cc.d_jobs, kv.second.size() * sizeof(BatchJob)));
+        KD_HIP(hipMemcpy(cc.d_jobs, kv.second.data(), kv.second.size() * sizeof(BatchJob), hipMemcpyHostToDevice));
+        auto it = mlp.find(kv.first);
+        if (it != mlp.end()) {
+            cc.n_mlp = int(it->second.size());
+            cc.mlp_tiles = it->second.back().tile_base + (it->second.back().Q + 63) / 64;
+            KD_HIP(hipMalloc(&cc.d_mlp, it->second.size() * sizeof(MlpJob)));
+            KD_HIP(hipMemcpy(cc.d_mlp, it->second.data(), it->second.size() * sizeof(MlpJob), hipMemcpyHostToDevice));
+        }
+        const ClassLayout L = class_layout(cc, b->device);
+        KD_HIP(hipMalloc(&cc.ws, L.sort_b + L.rec_b + L.cur_b + L.heavy_b + L.w0_b));
     }
-
-    // capture the whole batch as one graph (on a private stream when the
-    // caller passes the default stream, which cannot be captured)
-    hipStream_t cs = reinterpret_cast<hipStream_t>(stream);
-    hipStream_t own = nullptr;
-    if (!cs) {
-        KD_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
-        cs = own;
-    }
-    auto fail = [&](kd_status st) {
-        if (own) (void)hipStreamDestroy(own);
-        return st;
-    };
-    // One graph branch per (dim, K) class: the classes are independent, so
-    // their persistent launches overlap and the long traversals that end one
-    // class run beside the next class's work.  Branch streams use the default
-    // priority; they fork from and join back into the capture stream.
-    std::vector<hipStream_t> side(b->classes.size(), nullptr);
-    std::vector<hipEvent_t> done(b->classes.size(), nullptr);
-    hipEvent_t fork = nullptr;
-    auto release = [&]() {
-        for (hipStream_t x : side)
-            if (x) (void)hipStreamDestroy(x);
-        for (hipEvent_t x : done)
-            if (x) (void)hipEventDestroy(x);
-        if (fork) (void)hipEventDestroy(fork);
-    };
-    hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-    for (size_t i = 0; i < side.size() && e == hipSuccess; ++i) {
-        e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&done[i], hipEventDisableTiming);
-    }
-    if (e != hipSuccess) {
-        release();
-        return fail(hip_error(e, "kd_batch_create: branch streams"));
-    }
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) {
-        release();
-        return fail(hip_error(e, "kd_batch_create: begin capture"));
-    }
-    for (size_t i = 0; i < b->empty_out.size(); ++i) {
-        const int64_t n = b->empty_n[i];
-        hipLaunchKernelGGL(batch_fill_empty, dim3(unsigned((n + 255) / 256)), dim3(256), 0, cs,
-                           b->empty_out[i].first, b->empty_out[i].second, n);
-    }
-    e = hipEventRecord(fork, cs);
-    for (size_t i = 0; i < b->classes.size() && s == KD_OK && e == hipSuccess; ++i) {
-        auto& c = b->classes[i];
-        hipStream_t bs = side[i];
-        e = hipStreamWaitEvent(bs, fork, 0);
-        if (e != hipSuccess) break;
-        char* ws = static_cast<char*>(c.ws);
-        const size_t sort_b = (batch_sort_scratch_bytes(c.n) + 255) & ~size_t(255);
-        const size_t rec_b = (size_t(c.n) * batch_rec_bytes() + 255) & ~size_t(255);
-        const uint32_t* perm = nullptr;
-        s = batch_sort(c.d_jobs, c.njobs, c.dim, c.n, plan.sort_bits, ws, bs, &perm);
-        if (s != KD_OK) break;
-        QueryPlan cp = plan;
-        cp.K = c.K;
-        s = run_batch_class(c.d_jobs, c.njobs, c.dim, c.K, c.n, perm, ws + sort_b,
-                            reinterpret_cast<uint32_t*>(ws + sort_b + rec_b), cp, device, bs);
-        if (s != KD_OK) break;
-        e = hipEventRecord(done[i], bs);
-        if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[i], 0);
-    }
-    hipGraph_t graph = nullptr;
-    const hipError_t ec = hipStreamEndCapture(cs, &graph);
-    release();
-    if (s == KD_OK && e != hipSuccess) s = hip_error(e, "kd_batch_create: branch capture");
-    e = ec;
-    if (s != KD_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return fail(s);
-    }
-    if (e != hipSuccess) return fail(hip_error(e, "kd_batch_create: end capture"));
-    b->graph = graph;
-    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) return fail(hip_error(e, "kd_batch_create: instantiate"));
-    if (own) (void)hipStreamDestroy(own);
+    s = capture_batch(b.get(), reinterpret_cast<hipStream_t>(stream));
+    if (s != KD_OK) return s;
     *out = b.release();
     return KD_OK;
 }
@@ -237,15 +332,125 @@ kd_status kd_batch_free(kd_batch b) {
     return KD_OK;
 }
 
-kd_status kd_knn_batched(const kd_job* jobs, int n_jobs, const kd_opts* opts, kd_stream stream) {
+kd_status kd_knn_batched(const kd_job* jobs, int n_jobs, kd_model model, const kd_opts* opts, kd_stream stream) {
     kd_batch b = nullptr;
-    kd_status s = kd_batch_create(jobs, n_jobs, opts, stream, &b);
+    kd_status s = kd_batch_create(jobs, n_jobs, model, opts, stream, &b);
     if (s != KD_OK) return s;
     s = kd_batch_run(b, stream);
     hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
     kd_batch_free(b);
     if (s != KD_OK) return s;
     if (e != hipSuccess) return hip_error(e, "kd_knn_batched: synchronize");
+    return KD_OK;
+}
+
+kd_status kd_batch_autotune(kd_batch b, int reps, kd_stream stream, kd_opts* class_opts, int* n_classes) {
+    if (!b) return set_error(KD_EINVAL, "kd_batch_autotune: batch is NULL");
+    if (reps < 1) reps = 3;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipStream_t own = nullptr;
+    if (!st) {
+        KD_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        st = own;
+    }
+    unsigned long long* d_sum = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (d_sum) (void)hipFree(d_sum);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (own) (void)hipStreamDestroy(own);
+    };
+    hipError_t e = hipMalloc(&d_sum, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_error(e, "kd_batch_autotune: setup");
+    }
+    // the checksum of a class's outputs after one run of its pipeline
+    auto checksum = [&](const kd_batch_s::Class& c, uint64_t* h) -> kd_status {
+        KD_HIP(hipMemsetAsync(d_sum, 0, sizeof(unsigned long long), st));
+        for (size_t j = 0; j < c.jobs.size(); ++j) {
+            const BatchJob& J = c.jobs[j];
+            const int64_t n = int64_t(J.Q) * J.k;
+            const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 1024));
+            hipLaunchKernelGGL(output_checksum, dim3(blocks), dim3(256), 0, st, J.out_idx, J.out_d2, n,
+                               uint64_t(j) << 40, d_sum);
+            KD_HIP(hipGetLastError());
+        }
+        unsigned long long v = 0;
+        KD_HIP(hipMemcpyAsync(&v, d_sum, sizeof(v), hipMemcpyDeviceToHost, st));
+        KD_HIP(hipStreamSynchronize(st));
+        *h = v;
+        return KD_OK;
+    };
+    kd_status s = KD_OK;
+    for (auto& c : b->classes) {
+        // candidates: workgroup size x waves per CU x Morton sort bits
+        const QueryPlan keep = c.plan;
+        QueryPlan best = keep;
+        float best_ms = INFINITY;
+        uint64_t ref = 0;
+        bool have_ref = false;
+        for (int block : {256, 512}) {
+            if (c.K >= 32 && block > 256) continue;
+            for (int wpc : {16, 24, 32}) {
+                for (int bits : {16, 24, 32}) {
+                    c.plan = keep;
+                    c.plan.block = block;
+                    c.plan.waves_per_cu = wpc;
+                    c.plan.sort_bits = bits;
+                    s = enqueue_class(c, b->device, st);  // warm-up, and the outputs to check
+                    uint64_t h = 0;
+                    if (s == KD_OK) s = checksum(c, &h);
+                    if (s == KD_OK && have_ref && h != ref)
+                        s = set_error(KD_EHIP, "kd_batch_autotune: launch options changed the results");
+                    if (s != KD_OK) break;
+                    ref = h;
+                    have_ref = true;
+                    hipError_t er = hipEventRecord(e0, st);
+                    for (int r = 0; r < reps && s == KD_OK && er == hipSuccess; ++r) s = enqueue_class(c, b->device, st);
+                    if (er == hipSuccess) er = hipEventRecord(e1, st);
+                    if (er == hipSuccess) er = hipEventSynchronize(e1);
+                    float ms = 0;
+                    if (er == hipSuccess) er = hipEventElapsedTime(&ms, e0, e1);
+                    if (s == KD_OK && er != hipSuccess) s = hip_error(er, "kd_batch_autotune: timing");
+                    if (s != KD_OK) break;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = c.plan;
+                    }
+                }
+                if (s != KD_OK) break;
+            }
+            if (s != KD_OK) break;
+        }
+        c.plan = s == KD_OK ? best : keep;
+        if (s != KD_OK) break;
+    }
+    if (s == KD_OK) s = capture_batch(b, reinterpret_cast<hipStream_t>(stream));
+    if (s == KD_OK && n_classes) {
+        const int cap = *n_classes;
+        *n_classes = int(b->classes.size());
+        for (int i = 0; class_opts && i < cap && i < int(b->classes.size()); ++i) {
+            const QueryPlan& p = b->classes[i].plan;
+            class_opts[i] = kd_opts{p.block, p.lds_levels, p.sort_bits, p.waves_per_cu,
+                                    p.heavy_default ? 0 : (p.heavy_trips > 0 ? p.heavy_trips : -1), p.prune};
+        }
+    }
+    cleanup();
+    return s;
+}
+
+kd_status kd_batch_info(kd_batch b, int* n_classes, int* class_dim, int* class_k, int64_t* class_queries, int cap) {
+    if (!b || !n_classes) return set_error(KD_EINVAL, "kd_batch_info: NULL argument");
+    *n_classes = int(b->classes.size());
+    for (int i = 0; i < cap && i < int(b->classes.size()); ++i) {
+        if (class_dim) class_dim[i] = b->classes[i].dim;
+        if (class_k) class_k[i] = b->classes[i].K;
+        if (class_queries) class_queries[i] = b->classes[i].n;
+    }
     return KD_OK;
 }
 

@@ -169,6 +169,25 @@ struct BatchJob {
     uint32_t slot_base;      // first class slot of the job
     uint32_t Q;
     int32_t vec_store;
+    int32_t learned;         // starts from the initial radius in worst0 (3-D jobs with a model)
+};
+
+// A batched job whose initial radii come from a radius model, as the MLP
+// kernel sees it: the job's class records [slot_base, slot_base + Q) (each
+// job's records are contiguous after the class sort) are tiles
+// tile_base .. tile_base + ceil(Q / 64) - 1 of the class.
+struct MlpJob {
+    const float* P;          // model parameters (4481 floats)
+    float lo[3], inv[3];     // input normalisation
+    float margin;
+    float R2;
+    uint32_t slot_base, Q, tile_base, pad;
+};
+struct BatchLearned {
+    const MlpJob* jobs;      // device table, ascending tile_base
+    int njobs;
+    uint32_t ntiles;
+    float* worst0;           // [class records]
 };
 
 // Learned-radius request: initial squared radius per query from the MLP
@@ -184,10 +203,14 @@ struct LearnedSpec {
 size_t batch_sort_scratch_bytes(int64_t n);
 kd_status batch_sort(const BatchJob* d_jobs, int njobs, int dim, uint32_t n, int sort_bits, void* ws,
                      hipStream_t st, const uint32_t** perm_out);
+// learned (nullable): initial radii of the class's 3-D jobs with a model;
+// heavy_rows (nullable): [batch_heavy_cap][2] hand-off list (NULL: no hand-off)
 kd_status run_batch_class(const BatchJob* d_jobs, int njobs, int dim, int K, uint32_t n, const uint32_t* perm,
-                          void* recs, uint32_t* counters, const QueryPlan& plan, int device, hipStream_t st);
+                          void* recs, uint32_t* counters, const QueryPlan& plan, int device, hipStream_t st,
+                          const BatchLearned* learned, int32_t* heavy_rows);
 size_t batch_rec_bytes();
-size_t batch_cursor_bytes();  // work cursors of one class launch
+size_t batch_cursor_bytes();  // hand-off count and work cursors of one class launch
+uint32_t batch_heavy_cap(int device);  // hand-off list entries of one class launch
 // Morton reorder of query slots (kd_sort.hip)
 size_t sort_scratch_bytes(int64_t Q, int dim);
 // device scratch of one kd_knn-family call (kd_traverse.hip)
@@ -219,12 +242,21 @@ kd_status knn_entry(kd_tree t, const float* queries, int64_t Q, int k, float max
                     float* out_d2, uint32_t* visited, const kd_opts* opts, kd_stream stream, const char* fn,
                     const FixedScratch* fixed = nullptr);
 
+// ---- radius models (kd_model.cpp) -------------------------------------------
+// The model's device parameters, normalisation and margin (R2, slots and tiles
+// left for the caller).
+kd_status model_view(kd_model m, MlpJob* out);
+
 // ---- MLP kernels (kd_mlp.hip) ---------------------------------------------
 constexpr int MLP_NPARAM = 4481;
 // Adam hyper-parameters of the trainer (float32 values)
 constexpr float MLP_ADAM_BETA1 = 0.9f, MLP_ADAM_BETA2 = 0.999f, MLP_ADAM_EPS = 1e-8f;
 hipError_t launch_mlp_worst0(const float* P, const float* lo, const float* inv, float margin, float R2,
                              const void* sq, uint32_t Q, float* worst0, hipStream_t st);
+// worst0 for the batched class records (32 bytes: x, y, z, w, row, job, pad)
+// of the jobs in the table; other records are left untouched
+hipError_t launch_mlp_worst0_jobs(const MlpJob* jobs, int njobs, uint32_t ntiles, const void* recs, float* worst0,
+                                  hipStream_t st);
 // worst0 for caller-layout queries [n][3], in caller order (recs: n x 16 bytes of scratch)
 hipError_t launch_mlp_worst0_rows(const float* P, const float* lo, const float* inv, float margin, float R2,
                                   const float* queries, uint32_t n, void* recs, float* worst0, hipStream_t st);

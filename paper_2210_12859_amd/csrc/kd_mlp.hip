@@ -356,6 +356,63 @@ __global__ __launch_bounds__(256) void mlp_worst0(const float* __restrict__ P, N
     }
 }
 
+// Inference for batched class records (32 bytes: x, y, z, w, row, job, pad),
+// one table entry per 3-D job with a model: tile t of the table (ascending
+// tile_base) covers that job's records slot_base + 64 (t - tile_base) ...;
+// the wave loads the job's weights when its model differs from the last.
+__global__ __launch_bounds__(256) void mlp_worst0_jobs(const MlpJob* __restrict__ jobs, int njobs, uint32_t ntiles,
+                                                       const float4* __restrict__ recs, float* __restrict__ worst0) {
+    const int lane = threadIdx.x & 63;
+    InferWeights W;
+    const float* loaded = nullptr;
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t tile = wave; tile < ntiles; tile += nwaves) {
+        int lo = 0, hi = njobs - 1;  // last job with tile_base <= tile
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_base <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const MlpJob& J = jobs[lo];
+        if (J.P != loaded) {
+            load_weights(J.P, lane, W);
+            loaded = J.P;
+        }
+        Norm nm;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            nm.lo[j] = J.lo[j];
+            nm.inv[j] = J.inv[j];
+        }
+        const uint32_t first = J.slot_base + (tile - J.tile_base) * 64u;
+        const uint32_t end = J.slot_base + J.Q;
+        float xs[4][3];
+#pragma unroll
+        for (int nq = 0; nq < 4; ++nq) {
+            xs[nq][0] = xs[nq][1] = xs[nq][2] = 0.0f;
+            const uint32_t i = first + 16u * nq + uint32_t(lane);
+            if (lane < 16 && i < end) {
+                const float4 v = recs[2 * size_t(i)];
+                xs[nq][0] = (v.x - nm.lo[0]) * nm.inv[0];
+                xs[nq][1] = (v.y - nm.lo[1]) * nm.inv[1];
+                xs[nq][2] = (v.z - nm.lo[2]) * nm.inv[2];
+            }
+        }
+        const float y = mlp_tile(W, xs, lane);
+        const uint32_t slot = first + uint32_t(lane);
+        if (slot < end) {
+            const float r0 = expf(y + J.margin);
+            float wv = J.R2;
+            if (__builtin_isfinite(r0) && r0 >= 0.0f) {
+                const float r2 = r0 * r0;
+                wv = r2 < J.R2 ? r2 : J.R2;
+            }
+            worst0[slot] = wv;
+        }
+    }
+}
+
 // Raw forward for tests: y[i] for caller-layout queries [n][3].
 __global__ __launch_bounds__(256) void mlp_predict(const float* __restrict__ P, Norm nm, const float* __restrict__ qs,
                                                    uint32_t n, float* __restrict__ y) {
@@ -579,6 +636,16 @@ hipError_t launch_mlp_worst0(const float* P, const float* lo, const float* inv, 
     if (Q == 0) return hipSuccess;
     hipLaunchKernelGGL(mlp_worst0, dim3(infer_grid(Q)), dim3(256), 0, st, P, make_norm(lo, inv), margin, R2,
                        reinterpret_cast<const float4*>(sq), Q, worst0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_worst0_jobs(const MlpJob* jobs, int njobs, uint32_t ntiles, const void* recs, float* worst0,
+                                  hipStream_t st) {
+    if (ntiles == 0 || njobs == 0) return hipSuccess;
+    uint32_t grid = (ntiles + 3) / 4;
+    if (grid > 768) grid = 768;
+    hipLaunchKernelGGL(mlp_worst0_jobs, dim3(grid), dim3(256), 0, st, jobs, njobs, ntiles,
+                       static_cast<const float4*>(recs), worst0);
     return hipGetLastError();
 }
 

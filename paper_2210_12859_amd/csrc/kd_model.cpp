@@ -75,6 +75,23 @@ kd_status upload_params(kd_model m) {
 
 }  // namespace kd
 
+namespace kd {
+kd_status model_view(kd_model m, MlpJob* out) {
+    if (!m || !m->d_params) return set_error(KD_EINVAL, "radius model is NULL or has no parameters");
+    int dev = 0;
+    KD_HIP(hipGetDevice(&dev));
+    if (dev != m->device) return set_error(KD_EINVAL, "radius model lives on another device");
+    *out = MlpJob{};
+    out->P = m->d_params;
+    for (int j = 0; j < 3; ++j) {
+        out->lo[j] = m->lo[j];
+        out->inv[j] = m->inv[j];
+    }
+    out->margin = m->margin;
+    return KD_OK;
+}
+}  // namespace kd
+
 using namespace kd;
 
 extern "C" {

@@ -777,8 +777,16 @@ struct CoopArgs {
     float* out_d2;
     const uint32_t* heavy_count;
     uint32_t heavy_cap;
-    const int32_t* heavy_rows;
+    const int32_t* heavy_rows;  // [heavy_cap] caller rows; batched: [heavy_cap][2] (job, row)
+    const BatchJob* jobs;       // batched hand-off: the tree and outputs come from the job (else NULL)
 };
+
+// depth of the cooperative subtrees for a tree of N points
+__host__ __device__ __forceinline__ int coop_depth(int32_t N) {
+    int levels = 0;
+    while (levels < 31 && (int64_t(1) << levels) <= int64_t(N)) ++levels;  // floor(log2 N) + 1
+    return levels - 1 - KD_COOP_SUB_LEVELS > 0 ? levels - 1 - KD_COOP_SUB_LEVELS : 0;
+}
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
 #pragma unroll
@@ -830,28 +838,61 @@ __device__ __forceinline__ float coop_bound(const uint64_t (&L)[K], int k) {
 
 template <int D, int K>
 __global__ __launch_bounds__(256) void knn_coop(CoopArgs a) {
-    const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);
-    const int32_t* __restrict__ ids = node_ids<D>(g1, a.N);
     const uint32_t lane = __lane_id();
     const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
     const uint32_t nheavy = *a.heavy_count < a.heavy_cap ? *a.heavy_count : a.heavy_cap;
-    const int32_t first_sub = int32_t(1) << a.T;  // ids of depth T: [2^T, 2^(T+1))
     for (uint32_t h = wave; h < nheavy; h += nwaves) {
-        const int32_t row = a.heavy_rows[h];
+        // the query's tree and outputs: the call's, or (batched) its job's
+        const TreeRec<D>* g1;
+        const float* boxes;
+        const float* queries;
+        int32_t box_below, N, k, row;
+        int T;
+        float R2;
+        int32_t* out_idx;
+        float* out_d2;
+        if (a.jobs) {
+            const BatchJob& J = a.jobs[__builtin_amdgcn_readfirstlane(a.heavy_rows[2 * h])];
+            row = __builtin_amdgcn_readfirstlane(a.heavy_rows[2 * h + 1]);
+            g1 = reinterpret_cast<const TreeRec<D>*>(J.nodes);
+            boxes = J.boxes;
+            box_below = J.box_below;
+            N = J.N;
+            T = coop_depth(J.N);
+            queries = J.queries;
+            k = J.k;
+            R2 = J.R2;
+            out_idx = J.out_idx;
+            out_d2 = J.out_d2;
+        } else {
+            row = a.heavy_rows[h];
+            g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);
+            boxes = a.boxes;
+            box_below = a.box_below;
+            N = a.N;
+            T = a.T;
+            queries = a.queries;
+            k = a.k;
+            R2 = a.R2;
+            out_idx = a.out_idx;
+            out_d2 = a.out_d2;
+        }
+        const int32_t* __restrict__ ids = node_ids<D>(g1, N);
+        const int32_t first_sub = int32_t(1) << T;  // ids of depth T: [2^T, 2^(T+1))
         Lane<D, K> s;
 #pragma unroll
-        for (int j = 0; j < D; ++j) s.q[j] = a.queries[int64_t(row) * D + j];
+        for (int j = 0; j < D; ++j) s.q[j] = queries[int64_t(row) * D + j];
         s.row = row;
         s.vis = 0;
-        lane_reset<D, K>(s, a.k, a.R2);
+        lane_reset<D, K>(s, k, R2);
         s.curr = 0;
         int32_t stop = 0;
         // wave-uniform walk of the top levels (the same state machine); a
         // depth-T node it steps into goes to an idle lane as a whole subtree
         int32_t tcurr = 1, tprev = 0;
         bool top_done = false;
-        float bound = a.R2;
+        float bound = R2;
         uint32_t trip = 0;
         for (;;) {
             uint64_t idle = wave_ballot(s.curr == 0);
@@ -893,9 +934,9 @@ __global__ __launch_bounds__(256) void knn_coop(CoopArgs a) {
                 const float sd = dim.template rot<0>(dx);
                 const int32_t close_c = (tcurr << 1) | (sd > 0.0f ? 1 : 0);
                 const int32_t far_c = close_c ^ 1;
-                const bool far_ok = far_c <= a.N && sd * sd <= bound;
+                const bool far_ok = far_c <= N && sd * sd <= bound;
                 int32_t next;
-                if (from_parent && close_c <= a.N) next = close_c;
+                if (from_parent && close_c <= N) next = close_c;
                 else if ((from_parent || tprev == close_c) && far_ok) next = far_c;
                 else next = tcurr >> 1;
                 tprev = tcurr;
@@ -908,30 +949,30 @@ __global__ __launch_bounds__(256) void knn_coop(CoopArgs a) {
                 int32_t idx;
                 float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
                 load_tree<D>(g1 + s.curr, c, idx, anc);
-                const bool skip = a.boxes != nullptr && s.far_entry && s.curr < a.box_below &&
-                                  box_d2<D>(a.boxes, s.curr, s.q) > fminf(key_d2(s.L[K - 1]), bound);
-                lane_step<D, K, fused_levels(D), true>(s, c, idx, ids, anc, a.N, bound, stop, skip);
+                const bool skip = boxes != nullptr && s.far_entry && s.curr < box_below &&
+                                  box_d2<D>(boxes, s.curr, s.q) > fminf(key_d2(s.L[K - 1]), bound);
+                lane_step<D, K, fused_levels(D), true>(s, c, idx, ids, anc, N, bound, stop, skip);
                 if (s.curr == stop) s.curr = 0;
             }
             // the wave-wide bound is refreshed every 8 trips (a stale bound
             // is larger, so still safe to prune with)
-            if ((++trip & 7u) == 0) bound = coop_bound<K>(s.L, a.k);
+            if ((++trip & 7u) == 0) bound = coop_bound<K>(s.L, k);
         }
         // merge: k rounds of the wave-wide smallest key; the lane holding it
         // (keys of points are unique) drops it.  Slots below K - k hold no
         // point: they are set to the largest key first.
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            if (j < K - a.k) s.L[j] = ~uint64_t(0);
-        for (int r = 0; r < a.k; ++r) {
+            if (j < K - k) s.L[j] = ~uint64_t(0);
+        for (int r = 0; r < k; ++r) {
             uint64_t head = s.L[0];
 #pragma unroll
             for (int j = 1; j < K; ++j) head = s.L[j] < head ? s.L[j] : head;
             const uint64_t m = wave_min_u64(head);
             const bool empty = uint32_t(m) == SENT_IDX;
             if (lane == 0) {
-                a.out_idx[int64_t(row) * a.k + r] = empty ? -1 : int32_t(uint32_t(m));
-                if (a.out_d2) a.out_d2[int64_t(row) * a.k + r] = empty ? __builtin_inff() : key_d2(m);
+                out_idx[int64_t(row) * k + r] = empty ? -1 : int32_t(uint32_t(m));
+                if (out_d2) out_d2[int64_t(row) * k + r] = empty ? __builtin_inff() : key_d2(m);
             }
             if (!empty && head == m) {
 #pragma unroll
@@ -1089,6 +1130,11 @@ struct BatchArgs {
     const BRec* recs;
     uint32_t Q;
     uint32_t* counter;
+    const float* worst0;     // learned kernels: initial squared radius per record (jobs with a model)
+    uint32_t heavy_trips;    // trip budget per query before the hand-off, 0 = none
+    uint32_t heavy_cap;
+    uint32_t* heavy_count;
+    int32_t* heavy_rows;     // [heavy_cap][2]: (job, row)
 };
 
 template <int D, int K>
@@ -1102,12 +1148,16 @@ struct JobLane {
     int32_t* oi;
     float* od;
     int32_t vec;
+    int32_t job;
+    float R2;
 };
 
-template <int D, int K>
+template <int D, int K, bool LEARNED = false>
 __device__ __forceinline__ void batch_start(Lane<D, K>& s, JobLane<D, K>& j, const BatchJob* jobs,
-                                            const BRec& r) {
+                                            const BRec& r, float w0 = 0.0f, uint32_t wtrip = 0) {
     const BatchJob& J = jobs[r.job];
+    j.job = r.job;
+    j.R2 = J.R2;
     j.g1 = reinterpret_cast<const TreeRec<D>*>(J.nodes);
     j.boxes = J.boxes;
     j.box_below = J.box_below;
@@ -1121,8 +1171,10 @@ __device__ __forceinline__ void batch_start(Lane<D, K>& s, JobLane<D, K>& j, con
     for (int d = 0; d < D; ++d) s.q[d] = r.c[d];
     s.row = r.row;
     s.vis = 0;
+    s.t0 = wtrip;
     s.fell_back = false;
-    lane_reset<D, K>(s, j.k, J.R2);
+    // learned: jobs with a model start from their initial radius
+    lane_reset<D, K>(s, j.k, LEARNED && J.learned ? w0 : J.R2);
 }
 
 template <int D, int K>
@@ -1165,7 +1217,7 @@ __device__ __forceinline__ BRec load_brec(const BRec* p) {
     return r;
 }
 
-template <int D, int K, int F>
+template <int D, int K, int F, bool LEARNED>
 __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
     const uint32_t lane = __lane_id();
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
@@ -1177,10 +1229,12 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
     // any slot left is worth stealing
     WorkSource ws(group_range(blockIdx.x, gridDim.x), gridDim.x, blockDim.x >> 6, a.Q, 1u);
     BRec chunk;
+    float chunk_w0 = 0.0f;
     uint32_t cpos = 0, cn = 0;
     Lane<D, K> s;
     s.curr = 0;  // active while curr != 0, as in the single-tree kernel
     JobLane<D, K> j;
+    uint32_t wtrip = 0;  // trips of this wave (wave-uniform)
     for (;;) {
         const uint64_t need = wave_ballot(s.curr == 0);
         if (need && !ws.exhausted && __popcll(need) >= KD_REFILL_MIN_BATCHED) {
@@ -1188,9 +1242,11 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
             const uint32_t rank = __popcll(need & lt_mask);
             const uint32_t take1 = n < cn - cpos ? n : cn - cpos;
             {
-                const BRec v = shfl_brec(chunk, int(cpos + (rank < take1 ? rank : 0)));
+                const int src = int(cpos + (rank < take1 ? rank : 0));
+                const BRec v = shfl_brec(chunk, src);
+                const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
                 if (s.curr == 0 && rank < take1) {
-                    batch_start<D, K>(s, j, a.jobs, v);
+                    batch_start<D, K, LEARNED>(s, j, a.jobs, v, vw, wtrip);
                 }
             }
             cpos += take1;
@@ -1198,13 +1254,18 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
                 uint32_t cb = 0, cn2 = 0;
                 ws.grab<true>(wa, lane, cb, cn2);
                 if (cn2) {
-                    if (lane < cn2) chunk = load_brec(a.recs + cb + lane);
+                    if (lane < cn2) {
+                        chunk = load_brec(a.recs + cb + lane);
+                        if (LEARNED) chunk_w0 = a.worst0[cb + lane];
+                    }
                     cn = cn2;
                     const uint32_t r2 = rank - take1;
                     const uint32_t take2 = n - take1 < cn2 ? n - take1 : cn2;
-                    const BRec v = shfl_brec(chunk, int(r2 < take2 ? r2 : 0));
+                    const int src = int(r2 < take2 ? r2 : 0);
+                    const BRec v = shfl_brec(chunk, src);
+                    const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
                     if (s.curr == 0 && rank >= take1 && r2 < take2) {
-                        batch_start<D, K>(s, j, a.jobs, v);
+                        batch_start<D, K, LEARNED>(s, j, a.jobs, v, vw, wtrip);
                     }
                     cpos = take2;
                 } else {
@@ -1214,6 +1275,7 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
             }
         }
         if (!wave_any(s.curr != 0)) break;
+        ++wtrip;
         if (s.curr != 0) {
             float c[D];
             int32_t idx;
@@ -1223,8 +1285,26 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
             const bool skip = s.far_entry && s.curr < j.box_below && j.boxes != nullptr &&
                               box_d2<D>(j.boxes, s.curr, s.q) > key_d2(s.L[K - 1]);
             const int32_t next = lane_step<D, K, F>(s, c, idx, j.ids, anc, j.N, 0.0f, 0, skip);
-            if (next == 0) {
-                batch_finish<D, K>(s, j);
+            bool handed = false;
+            // over the trip budget (checked every 16th wave trip, once per
+            // query): the cooperative kernel finishes the query from R2
+            if (a.heavy_trips && (wtrip & 15u) == 0 && next != 0 && wtrip - s.t0 - a.heavy_trips < 16u) {
+                const uint32_t pos = atomicAdd(a.heavy_count, 1u);
+                if (pos < a.heavy_cap) {
+                    a.heavy_rows[2 * pos] = j.job;
+                    a.heavy_rows[2 * pos + 1] = s.row;
+                    s.curr = 0;
+                    handed = true;
+                }
+            }
+            if (!handed && next == 0) {
+                if (LEARNED && lane_needs_restart<D, K>(s, j.R2)) {
+                    // fewer than k points inside the initial radius: again from R2
+                    s.fell_back = true;
+                    lane_reset<D, K>(s, j.k, j.R2);
+                } else {
+                    batch_finish<D, K>(s, j);
+                }
             }
         }
     }
@@ -1232,7 +1312,14 @@ __global__ __launch_bounds__(max_block(K)) void knn_batched(BatchArgs a) {
 
 template <int D, int K>
 hipError_t launch_batched(const BatchArgs& a, int block, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((knn_batched<D, K, fused_levels(D)>), dim3(grid), dim3(block), 0, st, a);
+    // learned-radius kernels exist for 3-D jobs only (the model is 3-D)
+    if constexpr (D == 3) {
+        if (a.worst0) {
+            hipLaunchKernelGGL((knn_batched<D, K, fused_levels(D), true>), dim3(grid), dim3(block), 0, st, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((knn_batched<D, K, fused_levels(D), false>), dim3(grid), dim3(block), 0, st, a);
     return hipGetLastError();
 }
 
@@ -1253,7 +1340,7 @@ hipError_t dispatch_batched_k(int K, const BatchArgs& a, int block, int grid, hi
 template <int D>
 hipError_t occupancy_batched_k(int K, int block, int* occ) {
     switch (K) {
-#define KD_OCCB(KK) case KK: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, knn_batched<D, KK, fused_levels(D)>, block, 0);
+#define KD_OCCB(KK) case KK: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, knn_batched<D, KK, fused_levels(D), D == 3>, block, 0);
         KD_OCCB(1) KD_OCCB(2) KD_OCCB(4) KD_OCCB(8) KD_OCCB(16) KD_OCCB(32) KD_OCCB(64)
 #undef KD_OCCB
     }
@@ -1290,12 +1377,16 @@ hipError_t launch_radius_to_worst0(int D, const float* r0, const void* sq, uint3
 }  // namespace
 
 size_t batch_rec_bytes() { return sizeof(BRec); }
-size_t batch_cursor_bytes() { return size_t(MAX_GROUPS) * CURSOR_STRIDE * 4; }
+// hand-off count (one cache line), then the range cursors
+size_t batch_cursor_bytes() { return 256 + size_t(MAX_GROUPS) * CURSOR_STRIDE * 4; }
+uint32_t batch_heavy_cap(int device) { return uint32_t(device_info(device).cus) * 2u * 4u * KD_COOP_ROUNDS; }
 
-// One (dim, K) class of a batched call: gather into class records, zero the
-// range cursors, one persistent traversal launch.
+// One (dim, K) class of a batched call: gather into class records, initial
+// radii of the jobs with a model, zero the counters, one persistent traversal
+// launch, then the cooperative kernel for queries over the trip budget.
 kd_status run_batch_class(const BatchJob* d_jobs, int njobs, int dim, int K, uint32_t n, const uint32_t* perm,
-                          void* recs, uint32_t* counters, const QueryPlan& plan, int device, hipStream_t st) {
+                          void* recs, uint32_t* counters, const QueryPlan& plan, int device, hipStream_t st,
+                          const BatchLearned* learned, int32_t* heavy_rows) {
     if (n == 0) return KD_OK;
     const DeviceInfo& dev = device_info(device);
     const dim3 g((n + 255) / 256), b(256);
@@ -1305,6 +1396,11 @@ kd_status run_batch_class(const BatchJob* d_jobs, int njobs, int dim, int K, uin
         default: hipLaunchKernelGGL(batch_gather<4>, g, b, 0, st, d_jobs, njobs, perm, n, (BRec*)recs); break;
     }
     KD_HIP(hipGetLastError());
+    float* worst0 = nullptr;
+    if (learned && dim == 3) {
+        worst0 = learned->worst0;
+        KD_HIP(launch_mlp_worst0_jobs(learned->jobs, learned->njobs, learned->ntiles, recs, worst0, st));
+    }
     int block = plan.block;
     if (K >= 32 && block > 256) block = 256;
     int occ = 0;
@@ -1320,13 +1416,38 @@ kd_status run_batch_class(const BatchJob* d_jobs, int njobs, int dim, int K, uin
     if (grid > MAX_GROUPS) grid = MAX_GROUPS;
     if (grid > 8 && grid % 8) grid -= grid % 8;
     if (grid < 1) grid = 1;
-    const int ncur = int(grid) * int(CURSOR_STRIDE);
-    hipLaunchKernelGGL(zero_u32, dim3(unsigned((ncur + 255) / 256)), dim3(256), 0, st, counters, ncur);
+    // counters: hand-off count at word 0, range cursors from word 64
+    const int nzero = 64 + int(grid) * int(CURSOR_STRIDE);
+    hipLaunchKernelGGL(zero_u32, dim3(unsigned((nzero + 255) / 256)), dim3(256), 0, st, counters, nzero);
     KD_HIP(hipGetLastError());
-    BatchArgs a{d_jobs, reinterpret_cast<const BRec*>(recs), n, counters};
+    const bool use_boxes = plan.prune != 1;
+    const int heavy_trips = plan.heavy_default ? (use_boxes ? KD_DEFAULT_HEAVY_TRIPS_BOXES : KD_DEFAULT_HEAVY_TRIPS)
+                                               : plan.heavy_trips;
+    BatchArgs a = {};
+    a.jobs = d_jobs;
+    a.recs = reinterpret_cast<const BRec*>(recs);
+    a.Q = n;
+    a.counter = counters + 64;
+    a.worst0 = worst0;
+    if (heavy_trips > 0 && heavy_rows) {
+        a.heavy_trips = uint32_t(heavy_trips);
+        a.heavy_cap = batch_heavy_cap(device);
+        a.heavy_count = counters;
+        a.heavy_rows = heavy_rows;
+    }
     e = dim == 2 ? dispatch_batched_k<2>(K, a, block, int(grid), st)
       : dim == 3 ? dispatch_batched_k<3>(K, a, block, int(grid), st) : dispatch_batched_k<4>(K, a, block, int(grid), st);
     if (e != hipSuccess) return hip_error(e, "knn_batched launch");
+    if (a.heavy_trips) {
+        // handed-off queries, one wave each; the count is read on the device
+        CoopArgs c = {};
+        c.heavy_count = a.heavy_count;
+        c.heavy_cap = a.heavy_cap;
+        c.heavy_rows = heavy_rows;
+        c.jobs = d_jobs;
+        e = launch_coop(dim, K, c, dev.cus * 2, st);
+        if (e != hipSuccess) return hip_error(e, "knn_coop launch (batched)");
+    }
     return KD_OK;
 }
 
@@ -1522,9 +1643,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
         c.boxes = a.boxes;
         c.box_below = a.box_below;
         c.N = int32_t(t->N);
-        int levels = 0;
-        while (levels < 31 && (int64_t(1) << levels) <= t->N) ++levels;  // floor(log2 N) + 1
-        c.T = levels - 1 - KD_COOP_SUB_LEVELS > 0 ? levels - 1 - KD_COOP_SUB_LEVELS : 0;
+        c.T = coop_depth(int32_t(t->N));
         c.queries = queries;
         c.k = plan.k;
         c.R2 = plan.R2;

@@ -124,3 +124,86 @@ def test_batched_generated_jobs_equal_single_calls(oracle_lib):
         rows = rng.choice(len(Qs), 50, replace=False)
         bi, bd = oracle_lib.brute(P, Qs[rows], meta[t]["k"])
         assert np.array_equal(jobs[t]["out_idx"].cpu().numpy()[rows], bi)
+
+
+def _clustered_specs(seed=5):
+    """3-D and 2-D jobs with tight clusters and far-off queries (long chains),
+    plus a 4-D job, mixed k."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for N, D, k in [(40000, 3, 8), (25000, 3, 1), (30000, 2, 8), (20000, 4, 32), (15000, 3, 16)]:
+        c = rng.random((16, D))
+        P = (c[rng.integers(0, 16, N)] + 0.003 * rng.standard_normal((N, D))).astype(np.float32)
+        Qs = np.concatenate([(c[rng.integers(0, 16, 3000)] + 0.003 * rng.standard_normal((3000, D))),
+                             rng.random((1000, D))]).astype(np.float32)
+        specs.append((P, Qs, k, math.inf))
+    return specs
+
+
+@pytest.mark.parametrize("heavy", [4, 64, -1])
+def test_batched_handoff_exact(oracle_lib, heavy):
+    """Trip budgets that hand most long queries to the cooperative kernel:
+    every job equals the oracle, under both pruning rules."""
+    specs = _clustered_specs()
+    jobs, trees = _make_jobs(specs)
+    for prune in (1, 2):
+        print(f"[gpu] batched hand-off heavy_trips={heavy} prune={prune}", flush=True)
+        kd.kd_knn_batched(jobs, opts=dict(heavy_trips=heavy, prune=prune))
+        torch.cuda.synchronize()
+        _check_against_oracle(oracle_lib, specs, jobs)
+
+
+def test_batched_learned_exact(oracle_lib):
+    """3-D jobs start from a radius model: a model trained on one of the
+    trees serves as the call's model, another job carries its own, and a
+    model from an unrelated tree is used for a third; every job equals the
+    oracle and the single-tree learned call."""
+    specs = _clustered_specs(7)
+    jobs, trees = _make_jobs(specs)
+    P0, Q0, k0, _ = specs[0]
+    train0 = _t(datagen.gmm(1 << 16, 3, 11, n_centers=16, sigma=0.003))
+    m_call = kd.kd_radius_model_train(trees[0], train0, k0, epochs=3)
+    m_own = kd.kd_radius_model_train(trees[4], _t(specs[4][1]), specs[4][2], epochs=2)
+    u = datagen.uniform(20000, 3, 3)
+    tu = kd.kd_build(_t(u))
+    m_other = kd.kd_radius_model_train(tu, _t(datagen.uniform(1 << 14, 3, 4)), 1, epochs=2)
+    jobs[4]["model"] = m_own
+    jobs[1]["model"] = m_other
+    for heavy in (0, 8):
+        print(f"[gpu] batched learned heavy_trips={heavy}", flush=True)
+        for j in jobs:
+            j["out_idx"].fill_(-9)
+        kd.kd_knn_batched(jobs, model=m_call, opts=dict(heavy_trips=heavy))
+        torch.cuda.synchronize()
+        _check_against_oracle(oracle_lib, specs, jobs)
+    # the graph path (create once, replay) with the learned radii
+    b = kd.Batch(jobs, model=m_call)
+    for j in jobs:
+        j["out_idx"].fill_(-9)
+    b.run()
+    torch.cuda.synchronize()
+    _check_against_oracle(oracle_lib, specs, jobs)
+    b.close()
+    li, ld, _, _ = kd.kd_knn_learned(trees[0], m_call, jobs[0]["queries"], k0)
+    torch.cuda.synchronize()
+    assert torch.equal(li.reshape(jobs[0]["out_idx"].shape), jobs[0]["out_idx"])
+    for m in (m_call, m_own, m_other):
+        m.close()
+
+
+def test_batched_autotune_keeps_results(oracle_lib):
+    specs = _mixed_jobs(3)
+    jobs, trees = _make_jobs(specs)
+    b = kd.Batch(jobs)
+    groups = b.info()
+    print(f"[gpu] batched autotune over {len(groups)} groups", flush=True)
+    chosen = b.autotune(reps=1)
+    assert len(chosen) == len(groups)
+    for o in chosen:
+        assert o["block"] in (256, 512) and o["waves_per_cu"] in (16, 24, 32) and o["sort_bits"] in (16, 24, 32)
+    for j in jobs:
+        j["out_idx"].fill_(-3)
+    b.run()
+    torch.cuda.synchronize()
+    _check_against_oracle(oracle_lib, specs, jobs)
+    b.close()
