@@ -221,7 +221,8 @@ typedef struct {
     int64_t holdout;       /* last rows of train_q held out to set the margin;
                               0 = min(Qt/10, 100000) */
     float margin_quantile; /* margin = this quantile of held-out (label - y),
-                              0..1 (default 0.95) */
+                              0..1 (default 0.999: a restarted query runs twice,
+                              late in the launch, so few restarts pay) */
 } kd_train_opts;
 
 typedef struct {
@@ -247,10 +248,15 @@ typedef struct {
 kd_status kd_radius_model_train(kd_tree t, const float* train_q, int64_t Qt, int k, const kd_train_opts* opts,
                                 kd_model* out, kd_stream stream);
 
-/* kd_knn with the model's initial radius (see above).  visited (nullable,
- * device uint32 [Q]) counts processed nodes of both runs; stats (nullable,
- * HOST) receives the counts and stage times above, which synchronises the
- * stream. */
+/* kd_knn with the model's initial radius (see above).  The initial-radius
+ * run starts below the root: descending from the root while the split plane
+ * lies farther than the initial radius (fl(sd^2) > worst0), every skipped
+ * node's point and far subtree are farther than worst0 as well, so the run
+ * covers the subtree of the deepest node reached; the restart from R2 covers
+ * the whole tree.  visited (nullable, device uint32 [Q]) counts processed
+ * nodes of both runs; stats (nullable, HOST) receives the counts and stage
+ * times above (radius_ms includes the start-node descent), which
+ * synchronises the stream. */
 kd_status kd_knn_learned(kd_tree t, kd_model m, const float* queries, int64_t Q, int k, float maxRadius,
                          int32_t* out_idx, float* out_d2, uint32_t* visited, kd_stats* stats, const kd_opts* opts,
                          kd_stream stream);

@@ -332,7 +332,7 @@ class Model:
 
 
 def kd_radius_model_train(tree: Tree, train_q, k, epochs=20, batch=8192, lr=1e-3, seed=0, holdout=0,
-                          margin_quantile=0.95, stream=None) -> Model:
+                          margin_quantile=0.999, stream=None) -> Model:
     import torch
     _require(train_q, torch.float32, "train_q")
     o = KdTrainOpts(int(epochs), int(batch), float(lr), int(seed), int(holdout), float(margin_quantile))

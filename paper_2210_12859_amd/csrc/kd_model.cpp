@@ -105,7 +105,7 @@ kd_status kd_radius_model_train(kd_tree t, const float* train_q, int64_t Qt, int
     if (t->N < k) return set_error(KD_EINVAL, "kd_radius_model_train: tree has fewer than k points");
     if (Qt < 128 || Qt >= (int64_t(1) << 31)) return set_error(KD_EINVAL, "kd_radius_model_train: need 128 <= Qt < 2^31");
     if (!train_q) return set_error(KD_EINVAL, "kd_radius_model_train: train_q is NULL");
-    kd_train_opts opt{20, 8192, 1e-3f, 0, 0, 0.95f};
+    kd_train_opts opt{20, 8192, 1e-3f, 0, 0, 0.999f};
     if (o) opt = *o;
     if (opt.epochs < 0 || opt.batch < 64 || opt.batch > (1 << 20) || !(opt.lr > 0.0f) ||
         !(opt.margin_quantile >= 0.0f && opt.margin_quantile <= 1.0f) || opt.holdout < 0)

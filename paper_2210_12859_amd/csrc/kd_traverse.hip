@@ -77,6 +77,7 @@ struct TravArgs {
     int vec_store;           // outputs 16-byte aligned with k % 4 == 0: vector stores
     // learned-radius kernels
     const float* worst0;     // [Q] initial squared radius per slot
+    const int32_t* start;    // [Q] node id the slot's initial-radius run starts from
     uint32_t* fb_count;      // queries restarted from R2 (nullable)
     unsigned long long* vis_total;  // entered nodes summed over the launch (nullable, learned kernels)
     uint8_t* fb_flag;        // [Q] caller order, 1 = restarted from R2 (nullable)
@@ -297,6 +298,8 @@ struct Lane {
     float q[D];
     uint64_t L[K];
     int32_t curr, prev;
+    int32_t stop;      // the traversal ends on stepping to this node: 0 (root's parent), or the
+                       // parent of the start node of a learned initial-radius run
     int32_t row;
     uint32_t vis;
     uint32_t t0;       // the wave's trip count when the current query started
@@ -315,12 +318,13 @@ __device__ __forceinline__ void lane_reset(Lane<D, K>& s, int k, float w0) {
     for (int j = 0; j < K; ++j) s.L[j] = (j < K - k) ? uint64_t(0) : sent;
     s.curr = 1;   // root
     s.prev = 0;   // the root's parent
+    s.stop = 0;
     s.far_entry = false;
 }
 
 template <int D, int K, bool LEARNED>
 __device__ __forceinline__ void lane_start(Lane<D, K>& s, const TravArgs& a, const NodeRec<D>& qr, float w0,
-                                           uint32_t wtrip = 0) {
+                                           uint32_t wtrip = 0, int32_t start = 1) {
 #pragma unroll
     for (int j = 0; j < D; ++j) s.q[j] = qr.c[j];
     s.row = qr.idx;
@@ -328,6 +332,12 @@ __device__ __forceinline__ void lane_start(Lane<D, K>& s, const TravArgs& a, con
     s.t0 = wtrip;
     s.fell_back = false;
     lane_reset<D, K>(s, a.k, LEARNED ? w0 : a.R2);
+    if (LEARNED) {
+        // the initial-radius run covers the subtree of the start node only
+        s.curr = start;
+        s.prev = start >> 1;
+        s.stop = start >> 1;
+    }
 }
 
 // A finished learned run with fewer than k points inside worst0 < R2: its
@@ -635,6 +645,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
     // take queries from it by cross-lane shuffle.
     NodeRec<D> chunk;
     float chunk_w0 = 0.0f;
+    int32_t chunk_start = 1;
     uint32_t cpos = 0, cn = 0;
 
     // a lane is active while its curr is a node id (curr = 0: no query; the
@@ -654,8 +665,9 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                 const int src = int(cpos + (rank < take1 ? rank : 0));
                 const NodeRec<D> v = shfl_rec<D>(chunk, src);
                 const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
+                const int32_t vs = LEARNED ? __shfl(chunk_start, src) : 1;
                 if (s.curr == 0 && rank < take1) {
-                    lane_start<D, K, LEARNED>(s, a, v, vw, wtrip);
+                    lane_start<D, K, LEARNED>(s, a, v, vw, wtrip, vs);
                 }
             }
             cpos += take1;
@@ -665,7 +677,10 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                 if (cn2) {
                     if (lane < cn2) {
                         chunk = load_query<D>(sq + cb + lane);
-                        if (LEARNED) chunk_w0 = a.worst0[cb + lane];
+                        if (LEARNED) {
+                            chunk_w0 = a.worst0[cb + lane];
+                            chunk_start = a.start[cb + lane];
+                        }
                     }
                     cn = cn2;
                     const uint32_t r2 = rank - take1;
@@ -673,8 +688,9 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                     const int src = int(r2 < take2 ? r2 : 0);
                     const NodeRec<D> v = shfl_rec<D>(chunk, src);
                     const float vw = LEARNED ? __shfl(chunk_w0, src) : 0.0f;
+                    const int32_t vs = LEARNED ? __shfl(chunk_start, src) : 1;
                     if (s.curr == 0 && rank >= take1 && r2 < take2) {
-                        lane_start<D, K, LEARNED>(s, a, v, vw, wtrip);
+                        lane_start<D, K, LEARNED>(s, a, v, vw, wtrip, vs);
                     }
                     cpos = take2;
                 } else {
@@ -698,12 +714,14 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                 if (s.far_entry && s.curr < a.box_below)
                     skip = box_d2<D>(a.boxes, s.curr, s.q) > key_d2(s.L[K - 1]);
             }
-            const int32_t next = lane_step<D, K, F, false, BOX>(s, c, idx, ids, anc, a.N, 0.0f, 0, skip);
+            const int32_t stop = LEARNED ? s.stop : 0;
+            const int32_t next = lane_step<D, K, F, false, BOX>(s, c, idx, ids, anc, a.N, 0.0f, stop, skip);
+            const bool done = next == stop;
             bool handed = false;
             // every running lane steps once per wave trip, so a query's trip
             // count is the wave's count since it started; the budget is
             // checked every 16th wave trip (a scalar test), once per query
-            if (a.heavy_trips && (wtrip & 15u) == 0 && next != 0 && wtrip - s.t0 - a.heavy_trips < 16u) {
+            if (a.heavy_trips && (wtrip & 15u) == 0 && !done && wtrip - s.t0 - a.heavy_trips < 16u) {
                 // over budget: the cooperative kernel finishes this query,
                 // unless it already holds heavy_cap queries (then the lane
                 // goes on)
@@ -716,7 +734,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                     handed = true;
                 }
             }
-            if (!handed && next == 0) {
+            if (!handed && done) {
                 if (LEARNED && lane_needs_restart<D, K>(s, a.R2)) {
                     s.fell_back = true;
                     ++restarts;
@@ -724,6 +742,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                 } else {
                     if (LEARNED) vis_sum += s.vis;
                     lane_finish<D, K, LEARNED>(s, a);
+                    s.curr = 0;  // idle (a learned run may end at its start node's parent)
                 }
             }
         }
@@ -1363,6 +1382,56 @@ __global__ void radius_to_worst0(const float* __restrict__ r0_rows, const NodeRe
     worst0[i] = w;
 }
 
+// Start node of a learned initial-radius run.  Descending from the root, a
+// node whose split plane lies farther from the query than the initial radius
+// (fl(sd * sd) > worst0, strictly) has its own point and every point of its
+// far subtree farther than worst0 too: such a point p has d2 >= fl(sd * sd)
+// (rounding is monotone and d2 sums non-negative squares).  Only the close
+// child's subtree can then hold points within worst0, so the run may start at
+// the deepest node reached this way; a run that finds fewer than k points
+// within worst0 there restarts from the root at R2 as before.  At most
+// floor(log2 N) + 1 steps (ids double; N < 2^30).
+template <int D>
+__global__ void learned_start(const TreeRec<D>* __restrict__ g1, int32_t N, const NodeRec<D>* __restrict__ sq,
+                              const float* __restrict__ worst0, uint32_t Q, int32_t* __restrict__ start) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Q) return;
+    const NodeRec<D> r = sq[i];
+    const float w0 = worst0[i];
+    int32_t curr = 1;
+    for (;;) {
+        float c[D];
+        int32_t idx;
+        float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
+        load_tree<D>(g1 + curr, c, idx, anc);
+        const DimSel<D> dim(curr);
+        float dx[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) dx[j] = r.c[j] - c[j];
+        const float sd = dim.template rot<0>(dx);
+        if (!(sd * sd > w0)) break;
+        const int32_t cc = (curr << 1) | (sd > 0.0f ? 1 : 0);
+        if (cc > N) break;
+        curr = cc;
+    }
+    start[i] = curr;
+}
+
+hipError_t launch_learned_start(int D, const void* nodes, int32_t N, const void* sq, const float* worst0, uint32_t Q,
+                                int32_t* start, hipStream_t st) {
+    if (Q == 0) return hipSuccess;
+    const dim3 grid((Q + 255) / 256), block(256);
+    switch (D) {
+        case 2: hipLaunchKernelGGL(learned_start<2>, grid, block, 0, st, (const TreeRec<2>*)nodes, N,
+                                   (const NodeRec<2>*)sq, worst0, Q, start); break;
+        case 3: hipLaunchKernelGGL(learned_start<3>, grid, block, 0, st, (const TreeRec<3>*)nodes, N,
+                                   (const NodeRec<3>*)sq, worst0, Q, start); break;
+        default: hipLaunchKernelGGL(learned_start<4>, grid, block, 0, st, (const TreeRec<4>*)nodes, N,
+                                    (const NodeRec<4>*)sq, worst0, Q, start); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_radius_to_worst0(int D, const float* r0, const void* sq, uint32_t Q, float R2, float* worst0,
                                    hipStream_t st) {
     const dim3 grid((Q + 255) / 256), block(256);
@@ -1467,7 +1536,7 @@ size_t query_scratch_bytes(int64_t Q, int dim, bool sorted, bool learned, bool h
     const size_t sq_bytes = (size_t(Q) * rec_bytes(dim) + 255) & ~size_t(255);
     const size_t sort_bytes = sorted ? sort_scratch_bytes(Q, dim) : 0;
     const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
-    return head + sq_bytes + sort_bytes + (learned ? q4 : 0) + (handoff ? q4 : 0);
+    return head + sq_bytes + sort_bytes + (learned ? 2 * q4 : 0) + (handoff ? q4 : 0);
 }
 
 namespace {
@@ -1508,7 +1577,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
     const size_t sort_bytes = plan.sort_bits > 0 ? sort_scratch_bytes(Q, t->dim) : 0;
     const size_t q4 = (size_t(Q) * 4 + 255) & ~size_t(255);
-    const size_t learn_bytes = learned ? q4 : 0;
+    const size_t learn_bytes = learned ? 2 * q4 : 0;  // initial radii, start nodes
     const size_t ws_bytes = query_scratch_bytes(Q, t->dim, plan.sort_bits > 0, learned != nullptr, handoff);
     kd_status s = KD_OK;
     if (fixed) {
@@ -1534,6 +1603,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     void* sq = base + head;
     void* sort_ws = base + head + sq_bytes;
     float* worst0 = learned ? reinterpret_cast<float*>(base + head + sq_bytes + sort_bytes) : nullptr;
+    int32_t* start = learned ? reinterpret_cast<int32_t*>(base + head + sq_bytes + sort_bytes + q4) : nullptr;
     int32_t* heavy_rows = handoff ? reinterpret_cast<int32_t*>(base + head + sq_bytes + sort_bytes + learn_bytes)
                                   : nullptr;
     // range cursors, restart count, hand-off count, entered-node total (64-bit)
@@ -1569,6 +1639,8 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
         else
             e = launch_radius_to_worst0(t->dim, learned->r0, sq, uint32_t(Q), plan.R2, worst0, st);
         if (e != hipSuccess) return hip_error(e, "initial radius launch");
+        e = launch_learned_start(t->dim, t->d_nodes, int32_t(t->N), sq, worst0, uint32_t(Q), start, st);
+        if (e != hipSuccess) return hip_error(e, "start node launch");
         s = timing_end(st, evm, "mlp");
         if (s != KD_OK) return s;
     }
@@ -1599,6 +1671,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
                   (reinterpret_cast<uintptr_t>(out_d2) % 16 == 0);
     if (learned) {
         a.worst0 = worst0;
+        a.start = start;
         a.fb_count = fb_count;
         a.fb_flag = learned->fb_flag;
         a.vis_total = vis_total;
