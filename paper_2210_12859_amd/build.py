@@ -36,6 +36,7 @@ SOURCES = [
     ("kd_batch.cpp", True, []),
     ("kd_autotune.cpp", True, []),
     ("kd_noalloc.hip", True, []),
+    ("kd_build_gpu.hip", True, []),
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",

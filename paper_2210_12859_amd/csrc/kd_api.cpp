@@ -332,16 +332,63 @@ kd_status kd_build(const float* points, int64_t N, int dim, kd_stream stream, kd
     if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build: N out of range [0, 2^30 - 1]");
     if (dim < 2 || dim > 4) return set_error(KD_EINVAL, "kd_build: dim must be 2, 3 or 4");
     if (N > 0 && !points) return set_error(KD_EINVAL, "kd_build: points is NULL");
-    try {
-        std::vector<float> host(size_t(N) * dim);
-        if (N > 0) {
-            KD_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
-            KD_HIP(hipMemcpy(host.data(), points, host.size() * sizeof(float), hipMemcpyDeviceToHost));
-        }
-        return build_from_host(host.data(), N, dim, out);
-    } catch (const std::exception& e) {
-        return set_error(KD_ENOMEM, std::string("kd_build: ") + e.what());
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    bool finite = true;
+    kd_status s = check_points_finite(points, N, dim, st, &finite);
+    if (s != KD_OK) return s;
+    if (!finite) return set_error(KD_EINVAL, "kd_build: points contain NaN or inf");
+    std::unique_ptr<kd_tree_s> t(new (std::nothrow) kd_tree_s);
+    if (!t) return set_error(KD_ENOMEM, "kd_build: host allocation");
+    t->N = N;
+    t->dim = dim;
+    KD_HIP(hipGetDevice(&t->device));
+    for (int j = 0; j < 4; ++j) t->lo[j] = t->hi[j] = 0.0f;
+    if (N == 0) {
+        *out = t.release();
+        return KD_OK;
     }
+    try {
+        t->order.resize(size_t(N));
+    } catch (...) {
+        return set_error(KD_ENOMEM, "kd_build: host allocation");
+    }
+    // level order, node records and subtree boxes on the device
+    int32_t* d_order = nullptr;
+    KD_HIP(hipMalloc(&d_order, size_t(N) * 4));
+    struct FreeOrder {
+        int32_t* p;
+        ~FreeOrder() { (void)hipFree(p); }
+    } guard{d_order};
+    s = build_level_order_device(points, N, dim, d_order, st);
+    if (s != KD_OK) return s;
+    KD_HIP(hipMalloc(&t->d_nodes, node_buffer_bytes(dim, N)));
+    hipError_t e = hipMalloc(&t->d_boxes, box_buffer_bytes(dim, N));
+    if (e != hipSuccess) {
+        (void)hipFree(t->d_nodes);
+        return hip_error(e, "kd_build: boxes");
+    }
+    s = pack_tree_device(points, d_order, N, dim, t->d_nodes, static_cast<float*>(t->d_boxes), st);
+    float root_box[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (s == KD_OK) {
+        e = hipMemcpyAsync(t->order.data(), d_order, size_t(N) * 4, hipMemcpyDeviceToHost, st);
+        // the root's box is the bounding box of all points
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(root_box, static_cast<float*>(t->d_boxes) + box_words(dim), box_words(dim) * 4,
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) s = hip_error(e, "kd_build: read back");
+    }
+    if (s != KD_OK) {
+        (void)hipFree(t->d_nodes);
+        (void)hipFree(t->d_boxes);
+        return s;
+    }
+    for (int j = 0; j < dim; ++j) {
+        t->lo[j] = root_box[j];
+        t->hi[j] = root_box[box_words(dim) / 2 + j];
+    }
+    *out = t.release();
+    return KD_OK;
 }
 
 kd_status kd_build_order_host(const float* host_points, int64_t N, int dim, int32_t* host_order) {

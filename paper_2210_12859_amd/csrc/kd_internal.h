@@ -213,6 +213,20 @@ size_t batch_cursor_bytes();  // hand-off count and work cursors of one class la
 uint32_t batch_heavy_cap(int device);  // hand-off list entries of one class launch
 // Morton reorder of query slots (kd_sort.hip)
 size_t sort_scratch_bytes(int64_t Q, int dim);
+// Stable LSD radix sort of n (key, value) pairs on key bits [0, bits), 8 bits
+// per pass, ping-ponging between (k0, v0) and (k1, v1); *in_second tells
+// which pair holds the result.  ws holds sort_pairs_scratch_bytes(n).
+size_t sort_pairs_scratch_bytes(uint32_t n);
+kd_status sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n, int bits, void* ws,
+                     hipStream_t st, bool* in_second);
+// Canonical tree on the device (kd_build_gpu.hip): d_order[pos] = caller
+// index of the point at level-order position pos, for device points [N][dim].
+kd_status build_level_order_device(const float* d_pts, int64_t N, int dim, int32_t* d_order, hipStream_t st);
+// Node records and subtree boxes from device points and order (kd_build_gpu.hip).
+kd_status pack_tree_device(const float* d_pts, const int32_t* d_order, int64_t N, int dim, void* d_nodes,
+                           float* d_boxes, hipStream_t st);
+// *ok = no NaN or infinity among the N * dim device floats (synchronises).
+kd_status check_points_finite(const float* d_pts, int64_t N, int dim, hipStream_t st, bool* ok);
 // device scratch of one kd_knn-family call (kd_traverse.hip)
 size_t query_scratch_bytes(int64_t Q, int dim, bool sorted, bool learned, bool handoff);
 // Writes the queries as traversal records (NodeRec<dim>[Q]) into sq, in

@@ -416,6 +416,34 @@ kd_status batch_sort(const BatchJob* d_jobs, int njobs, int dim, uint32_t n, int
     return KD_OK;
 }
 
+size_t sort_pairs_scratch_bytes(uint32_t n) {
+    return (256 * size_t(sort_tiles(n)) + 256) * sizeof(uint32_t) + 512;
+}
+
+kd_status sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n, int bits, void* ws,
+                     hipStream_t st, bool* in_second) {
+    *in_second = false;
+    if (n <= 1 || bits <= 0) return KD_OK;
+    SortPass p = {};
+    p.n = n;
+    p.ntiles = sort_tiles(n);
+    p.hist = static_cast<uint32_t*>(ws);
+    p.totals = p.hist + size_t(256) * p.ntiles;
+    const int passes = (bits + 7) / 8;
+    for (int q = 0; q < passes; ++q) {
+        p.shift = 8 * q;
+        p.kin = k0;
+        p.vin = v0;
+        p.kout = k1;
+        p.vout = v1;
+        KD_HIP(launch_pass<0>(p, false, false, st));
+        uint32_t* tk = k0; k0 = k1; k1 = tk;
+        uint32_t* tv = v0; v0 = v1; v1 = tv;
+        *in_second = !*in_second;
+    }
+    return KD_OK;
+}
+
 size_t sort_scratch_bytes(int64_t Q, int dim) {
     const size_t ntiles = sort_tiles(uint32_t(Q));
     const size_t rb = dim == 4 ? 32 : 16;

@@ -91,6 +91,7 @@ def test_clustered_10m_subset_three_rules(oracle_lib):
     torch.cuda.synchronize()
     print("[gpu] clustered-10m: oracle tree and traversal of the subset", flush=True)
     order = oracle_lib.build_tree(P)
+    assert np.array_equal(tree.order(), order), "GPU-built tree differs from the oracle's"
     oi, od, _ = oracle_lib.knn(P, order, Qs[:n], k)
     _same(pi.cpu().numpy(), pd.cpu().numpy(), oi, od, "clustered-10m paper rule")
     _same(bi.cpu().numpy(), bd.cpu().numpy(), oi, od, "clustered-10m default")
@@ -156,6 +157,7 @@ def test_uniform4d_1m_q10m_subset(oracle_lib):
     fi, fd = kd.kd_fcp(tree, q)
     torch.cuda.synchronize()
     order = oracle_lib.build_tree(P)
+    assert np.array_equal(tree.order(), order), "GPU-built 4-D tree differs from the oracle's"
     oi, od, _ = oracle_lib.knn(P, order, Qs[:n], 8)
     _same(gi[:n].cpu().numpy(), gd[:n].cpu().numpy(), oi, od, "4-D k=8")
     _same(fi[:n].cpu().numpy(), fd[:n].cpu().numpy(), oi[:, 0], od[:, 0], "4-D fcp")
