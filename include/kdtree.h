@@ -370,10 +370,12 @@ kd_status kd_batch_info(kd_batch b, int* n_classes, int* class_dim, int* class_k
 /* --------------------------------------------------------------- autotune */
 
 /* Times the candidate launch options (workgroup size 256/512/1024 x waves
- * per CU 8..32 x Morton sort bits 0/16/24/32) on a sample of queries
- * (device float32 [Qs][dim]) with the given k and maxRadius, keeps the
- * fastest on the tree for k's list size, and returns it (best_out, best_ms
- * are HOST and nullable).  Results never depend on the choice.
+ * per CU 8..32 x Morton sort bits 0/16/24/32 x pruning rule x LDS levels
+ * 0/10) on a sample of queries (device float32 [Qs][dim]) with the given k
+ * and maxRadius, keeps the fastest on the tree for k's list size, and
+ * returns it (best_out, best_ms are HOST and nullable).  Results never depend
+ * on the choice: every candidate's results are checked equal to the first's
+ * (64-bit checksum of the result rows; a difference is KD_EHIP).
  * Synchronises the stream. */
 kd_status kd_autotune(kd_tree t, const float* sample_q, int64_t Qs, int k, float maxRadius, kd_opts* best_out,
                       float* best_ms, kd_stream stream);

@@ -67,15 +67,18 @@ kd_status kd_autotune(kd_tree t, const float* sample_q, int64_t Qs, int k, float
     }
     int32_t* idx = nullptr;
     float* d2 = nullptr;
+    unsigned long long* d_sum = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto cleanup = [&]() {
         if (idx) (void)hipFree(idx);
         if (d2) (void)hipFree(d2);
+        if (d_sum) (void)hipFree(d_sum);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
     hipError_t e = hipMalloc(&idx, size_t(Qs) * k * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc(&d2, size_t(Qs) * k * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&d_sum, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) {
@@ -84,12 +87,30 @@ kd_status kd_autotune(kd_tree t, const float* sample_q, int64_t Qs, int k, float
     }
     float best = INFINITY;
     kd_opts bo = cands.front();
+    uint64_t ref = 0;
+    bool have_ref = false;
     for (const kd_opts& o : cands) {
         kd_status s = knn_entry(t, sample_q, Qs, k, maxRadius, idx, d2, nullptr, &o, stream, "kd_autotune");
         if (s != KD_OK) {
             cleanup();
             return s;
         }
+        // every candidate must write the same results
+        unsigned long long h = 0;
+        e = hipMemsetAsync(d_sum, 0, sizeof(h), st);
+        if (e == hipSuccess) e = launch_output_checksum(idx, d2, Qs * k, 0, d_sum, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&h, d_sum, sizeof(h), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            cleanup();
+            return hip_error(e, "kd_autotune: checksum");
+        }
+        if (have_ref && h != ref) {
+            cleanup();
+            return set_error(KD_EHIP, "kd_autotune: launch options changed the results");
+        }
+        ref = h;
+        have_ref = true;
         float ms = 0;
         const int reps = 3;
         e = hipEventRecord(e0, st);

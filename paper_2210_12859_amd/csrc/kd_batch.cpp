@@ -80,6 +80,18 @@ __global__ void output_checksum(const int32_t* idx, const float* d2, int64_t n, 
     if ((threadIdx.x & 63) == 0 && acc) atomicXor(h, (unsigned long long)acc);
 }
 
+}  // namespace
+
+hipError_t launch_output_checksum(const int32_t* idx, const float* d2, int64_t n, uint64_t salt,
+                                  unsigned long long* h, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 1024));
+    hipLaunchKernelGGL(output_checksum, dim3(blocks), dim3(256), 0, st, idx, d2, n, salt, h);
+    return hipGetLastError();
+}
+
+namespace {
+
 void free_batch(kd_batch b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -373,11 +385,7 @@ kd_status kd_batch_autotune(kd_batch b, int reps, kd_stream stream, kd_opts* cla
         KD_HIP(hipMemsetAsync(d_sum, 0, sizeof(unsigned long long), st));
         for (size_t j = 0; j < c.jobs.size(); ++j) {
             const BatchJob& J = c.jobs[j];
-            const int64_t n = int64_t(J.Q) * J.k;
-            const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 1024));
-            hipLaunchKernelGGL(output_checksum, dim3(blocks), dim3(256), 0, st, J.out_idx, J.out_d2, n,
-                               uint64_t(j) << 40, d_sum);
-            KD_HIP(hipGetLastError());
+            KD_HIP(launch_output_checksum(J.out_idx, J.out_d2, int64_t(J.Q) * J.k, uint64_t(j) << 40, d_sum, st));
         }
         unsigned long long v = 0;
         KD_HIP(hipMemcpyAsync(&v, d_sum, sizeof(v), hipMemcpyDeviceToHost, st));

@@ -256,6 +256,13 @@ kd_status knn_entry(kd_tree t, const float* queries, int64_t Q, int k, float max
                     float* out_d2, uint32_t* visited, const kd_opts* opts, kd_stream stream, const char* fn,
                     const FixedScratch* fixed = nullptr);
 
+// ---- result checksum (kd_batch.cpp) -----------------------------------------
+// XORs into *h an order-independent, position-sensitive 64-bit hash of n
+// result slots (index, and d2 bits when d2 is not NULL); the autotuners
+// check with it that every candidate writes the same results.
+hipError_t launch_output_checksum(const int32_t* idx, const float* d2, int64_t n, uint64_t salt,
+                                  unsigned long long* h, hipStream_t st);
+
 // ---- radius models (kd_model.cpp) -------------------------------------------
 // The model's device parameters, normalisation and margin (R2, slots and tiles
 // left for the caller).
