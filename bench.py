@@ -288,6 +288,76 @@ def bench_batched(kd, datagen, args):
                       f"GMM-64, k in {{1,8,32}}, Q = N, seed 42; hipGraph replay per step"}
 
 
+# The paper's Table 1 (RTX 3090 Ti, uniform float4 points in [0,1]^4, 10M
+# uniform queries; queries/s).  Context only: another GPU, another generation.
+PAPER_TABLE1 = {
+    1_000: [888e6, 563e6, 359e6, 48e6, 14e6, 5.2e9, 6.6e9, 4.0e9, 1.8e9],
+    10_000: [664e6, 407e6, 262e6, 29.5e6, 8.7e6, 3.3e9, 3.9e9, 3.3e9, 1.6e9],
+    100_000: [396e6, 184e6, 122e6, 20.6e6, 6.0e6, 1.7e9, 1.8e9, 1.7e9, 1.1e9],
+    1_000_000: [100e6, 42.1e6, 26.6e6, 7.5e6, 2.9e6, 334e6, 338e6, 282e6, 255e6],
+    10_000_000: [44e6, 19.3e6, 12.3e6, 5.0e6, 2.3e6, 58.2e6, 58.5e6, 52.8e6, 51e6],
+    100_000_000: [36e6, 16.5e6, 10.8e6, 4.7e6, 2.1e6, 19.1e6, 16.6e6, 14.2e6, 13.8e6],
+    200_000_000: [34.8e6, 16.2e6, 10.6e6, 4.5e6, 2.1e6, 16.7e6, 12.2e6, 9.2e6, 8.9e6],
+}
+PAPER_COLUMNS = [(1, math.inf), (4, math.inf), (8, math.inf), (20, math.inf), (50, math.inf),
+                 (4, 0.01), (8, 0.01), (20, 0.01), (50, 0.01)]  # (k, maxRadius); k = 1 is fcp
+
+
+def paper_grid(args):
+    """The shape of the paper's Table 1 on this GPU: 4-D uniform points in
+    [0,1)^4, N from 1K to 200M, 10M uniform queries, fcp and kNN k in
+    {4, 8, 20, 50} unbounded and within 0.01; queries/s of one call (query
+    reorder + traversal), under the paper's pruning rule and the library
+    default, each checked on sampled rows against the oracle's brute force."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2210_12859_amd as kd
+    from paper_2210_12859_amd import datagen
+    dev = torch.device("cuda:0")
+    Qs = datagen.uniform(10_000_000, 4, 1)
+    q = torch.from_numpy(Qs).to(dev)
+    stream = torch.cuda.current_stream()
+    rows_out = []
+    for N in sorted(PAPER_TABLE1):
+        P = datagen.uniform(N, 4, 0)
+        tree = kd.kd_build(torch.from_numpy(P).to(dev))
+        nrows = 32 if N <= 10_000_000 else 4
+        rows = np.random.default_rng(N).choice(len(Qs), nrows, replace=False)
+        for col, (k, maxr) in enumerate(PAPER_COLUMNS):
+            oi = torch.empty((len(Qs), k), dtype=torch.int32, device=dev)
+            od = torch.empty((len(Qs), k), dtype=torch.float32, device=dev)
+            cell = {"N": N, "k": k, "maxRadius": maxr, "paper_qps": PAPER_TABLE1[N][col]}
+            bi, bd = oracle.brute(P, Qs[rows], k, maxr)
+            for name, opts in (("paper_rule", {"prune": 1}), ("default", None)):
+                kd.kd_knn_ex(tree, q, k, maxr, out_idx=oi, out_d2=od, opts=opts)
+                torch.cuda.synchronize()
+                r = torch.from_numpy(rows).to(dev)
+                ok = bool(np.array_equal(oi[r].cpu().numpy(), bi) and
+                          np.array_equal(od[r].cpu().numpy().view(np.uint32), bd.view(np.uint32)))
+                reps = 3
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    kd.kd_knn_ex(tree, q, k, maxr, out_idx=oi, out_d2=od, opts=opts)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                cell[name + "_qps"] = len(Qs) / (ms / 1e3)
+                cell[name + "_exact_on_sample"] = ok
+            log(f"paper grid N={N} k={k} maxR={maxr:g}: {cell['paper_rule_qps'] / 1e6:.1f} M q/s (paper rule), "
+                f"{cell['default_qps'] / 1e6:.1f} M q/s (default), paper {cell['paper_qps'] / 1e6:.1f} M q/s")
+            rows_out.append(cell)
+            del oi, od
+        tree.close()
+        del P
+    print(json.dumps({"paper_grid": rows_out, "queries": len(Qs),
+                      "workload": "uniform float32 4-D points in [0,1)^4 (seed 0); 10,000,000 uniform queries (seed 1)",
+                      "note": "paper_qps: the paper's Table 1, RTX 3090 Ti; context only"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,9 +375,14 @@ def main():
     ap.add_argument("--batch-nmax", type=int, default=2000000, help="largest tree of the batched measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM counters)")
+    ap.add_argument("--paper-grid", action="store_true",
+                    help="only run the shape of the paper's Table 1 (4-D, N 1K..200M, 10M queries)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.paper_grid:
+        paper_grid(args)
         return
 
     if args.gpus != 1:

@@ -161,4 +161,13 @@ def test_uniform4d_1m_q10m_subset(oracle_lib):
     oi, od, _ = oracle_lib.knn(P, order, Qs[:n], 8)
     _same(gi[:n].cpu().numpy(), gd[:n].cpu().numpy(), oi, od, "4-D k=8")
     _same(fi[:n].cpu().numpy(), fd[:n].cpu().numpy(), oi[:, 0], od[:, 0], "4-D fcp")
+    # the other cells of the paper's table at this N (k = 4, 20, 50, unbounded
+    # and within 0.01), both pruning rules, on the first 2^18 rows
+    m = 1 << 18
+    for k, maxr in ((4, math.inf), (20, math.inf), (50, math.inf), (4, 0.01), (20, 0.01), (50, 0.01)):
+        oi, od, _ = oracle_lib.knn(P, order, Qs[:m], k, maxr)
+        for opts in (PLAIN, None):
+            ai, ad, _ = kd.kd_knn_ex(tree, q[:m], k, maxr, opts=opts)
+            torch.cuda.synchronize()
+            _same(ai.cpu().numpy(), ad.cpu().numpy(), oi, od, f"4-D k={k} maxR={maxr} opts={opts}")
     tree.close()
