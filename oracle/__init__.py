@@ -8,7 +8,9 @@ imports the other.
 Contents
   * ``kd_oracle.c`` (loaded through ctypes): canonical build, the ordered
     recursive traversal of the paper's Sec. 3.1, brute force, the
-    learned-radius rule, threaded batch drivers.
+    learned-radius rule, radius and box queries by their plain definitions
+    (the "find all points within a radius / inside a box" variants of Sec. 3),
+    threaded batch drivers.
   * ``mlp_ref``: float64 reference of the radius-prediction MLP with the
     bfloat16 rounding points of the GPU kernels emulated.
 
@@ -74,6 +76,10 @@ def _load():
     lib.oracle_brute_batch.restype = i32
     lib.oracle_knn_learned_batch.argtypes = [P, P, i64, i32, P, i64, i32, f32, P, P, P, P, P, i32]
     lib.oracle_knn_learned_batch.restype = i32
+    lib.oracle_radius_batch.argtypes = [P, i64, i32, P, i64, i32, f32, P, P, P, i32]
+    lib.oracle_radius_batch.restype = i32
+    lib.oracle_box_batch.argtypes = [P, i64, i32, P, i64, i32, P, P, i32]
+    lib.oracle_box_batch.restype = i32
     _lib = lib
     return lib
 
@@ -187,3 +193,41 @@ def knn_learned(points, order, queries, k, r0, max_radius=np.inf, nthreads=None)
     if rc != 0:
         raise ValueError("oracle_knn_learned_batch failed")
     return oi, od, vis, fb.astype(bool)
+
+
+def radius(points, queries, max_radius, k=0, nthreads=None):
+    """All points within max_radius (d2 <= fl32(maxR^2)) of each query, by the
+    plain definition.  Returns (count[Q], idx[Q][k], d2[Q][k]): the number of
+    such points and the k nearest of them by (d2, caller index)."""
+    P = _f32c(points)
+    Qs = _f32c(queries)
+    N, D = P.shape if P.size else (0, Qs.shape[1])
+    Q = Qs.shape[0]
+    oi = np.empty((Q, k), np.int32)
+    od = np.empty((Q, k), np.float32)
+    cnt = np.empty(Q, np.int64)
+    rc = _load().oracle_radius_batch(_ptr(P), N, D, _ptr(Qs), Q, k, sq_radius(max_radius),
+                                     _ptr(oi) if k else None, _ptr(od) if k else None, _ptr(cnt),
+                                     nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_radius_batch failed")
+    return cnt, oi, od
+
+
+def box(points, lo, hi, k=0, nthreads=None):
+    """All points inside the axis-aligned boxes [lo, hi] (inclusive in every
+    dimension), by the plain definition.  Returns (count[Q], idx[Q][k]): the
+    number of such points and the k smallest caller indices of them."""
+    P = _f32c(points)
+    lo = _f32c(lo)
+    hi = _f32c(hi)
+    Q, D = lo.shape
+    N = P.shape[0] if P.size else 0
+    boxes = np.ascontiguousarray(np.stack([lo, hi], axis=1), np.float32)  # [Q][2][D]
+    oi = np.empty((Q, k), np.int32)
+    cnt = np.empty(Q, np.int64)
+    rc = _load().oracle_box_batch(_ptr(P), N, D, _ptr(boxes), Q, k, _ptr(oi) if k else None, _ptr(cnt),
+                                  nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_box_batch failed")
+    return cnt, oi

@@ -252,10 +252,43 @@ void oracle_brute_one(const float* P, int64_t N, int D, const float* q, int k, f
     free(lidx);
 }
 
+/* -------------------------------------------------- range queries (brute) */
+
+/* All points within the radius (d2 <= R2, the definition above): returns
+ * their number; the k smallest of them by (d2, caller index) go to
+ * out_idx / out_d2 as in oracle_brute_one (k = 0: count only). */
+int64_t oracle_radius_one(const float* P, int64_t N, int D, const float* q, float R2, int k,
+                          int32_t* out_idx, float* out_d2) {
+    int64_t count = 0;
+    for (int64_t i = 0; i < N; ++i)
+        if (sqdist(q, P + i * D, D) <= R2) ++count;
+    if (k > 0) oracle_brute_one(P, N, D, q, k, R2, out_idx, out_d2);
+    return count;
+}
+
+/* All points inside the axis-aligned box [lo, hi] (lo[j] <= p[j] <= hi[j] in
+ * every dimension, inclusive): returns their number; the k smallest caller
+ * indices of them, ascending, go to out_idx, -1 after them (k = 0: count
+ * only).  Scanning indices upwards, the first k found are the smallest. */
+int64_t oracle_box_one(const float* P, int64_t N, int D, const float* lo, const float* hi, int k,
+                       int32_t* out_idx) {
+    int64_t count = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        int in = 1;
+        for (int j = 0; j < D; ++j)
+            if (!(lo[j] <= P[i * D + j] && P[i * D + j] <= hi[j])) in = 0;
+        if (!in) continue;
+        if (count < k) out_idx[count] = (int32_t)i;
+        ++count;
+    }
+    for (int64_t j = count; j < k; ++j) out_idx[j] = -1;
+    return count;
+}
+
 /* ------------------------------------------------- threaded batch drivers */
 
 typedef struct {
-    int mode; /* 0 tree, 1 brute, 2 learned */
+    int mode; /* 0 tree, 1 brute, 2 learned, 3 radius, 4 box */
     const float* P;
     const int32_t* order;
     int64_t N;
@@ -271,6 +304,7 @@ typedef struct {
     int32_t* fell_back;
     int64_t next;       /* shared chunk cursor */
     pthread_mutex_t mu;
+    int64_t* count;     /* radius / box: points found per query */
 } batch_job;
 
 #define CHUNK 4096
@@ -285,6 +319,17 @@ static void* batch_worker(void* arg) {
         if (lo >= b->Q) break;
         int64_t hi = lo + CHUNK < b->Q ? lo + CHUNK : b->Q;
         for (int64_t i = lo; i < hi; ++i) {
+            if (b->mode == 3 || b->mode == 4) {
+                /* radius: queries [Q][D]; box: [Q][2][D] (low corner, high corner) */
+                int32_t* oi = b->out_idx ? b->out_idx + i * b->k : NULL;
+                float* od = b->out_d2 ? b->out_d2 + i * b->k : NULL;
+                if (b->mode == 3)
+                    b->count[i] = oracle_radius_one(b->P, b->N, b->D, b->Qp + i * b->D, b->R2, b->k, oi, od);
+                else
+                    b->count[i] = oracle_box_one(b->P, b->N, b->D, b->Qp + i * 2 * b->D,
+                                                 b->Qp + i * 2 * b->D + b->D, b->k, oi);
+                continue;
+            }
             const float* q = b->Qp + i * b->D;
             int32_t* oi = b->out_idx + i * b->k;
             float* od = b->out_d2 ? b->out_d2 + i * b->k : NULL;
@@ -345,5 +390,21 @@ int oracle_knn_learned_batch(const float* P, const int32_t* order, int64_t N, in
                              int64_t* visited, int32_t* fell_back, int nthreads) {
     if (k < 1 || N < 0 || Q < 0) return -1;
     batch_job b = {2, P, order, N, D, queries, Q, k, R2, r0, out_idx, out_d2, visited, fell_back};
+    return run_batch(&b, nthreads);
+}
+
+int oracle_radius_batch(const float* P, int64_t N, int D, const float* queries, int64_t Q, int k, float R2,
+                        int32_t* out_idx, float* out_d2, int64_t* count, int nthreads) {
+    if (k < 0 || N < 0 || Q < 0) return -1;
+    batch_job b = {3, P, NULL, N, D, queries, Q, k, R2, NULL, out_idx, out_d2, NULL, NULL};
+    b.count = count;
+    return run_batch(&b, nthreads);
+}
+
+int oracle_box_batch(const float* P, int64_t N, int D, const float* boxes, int64_t Q, int k, int32_t* out_idx,
+                     int64_t* count, int nthreads) {
+    if (k < 0 || N < 0 || Q < 0) return -1;
+    batch_job b = {4, P, NULL, N, D, boxes, Q, k, 0.0f, NULL, out_idx, NULL, NULL, NULL};
+    b.count = count;
     return run_batch(&b, nthreads);
 }
