@@ -201,6 +201,41 @@ kd_status kd_workspace_size(int64_t Q, int k, int flags, size_t* bytes);
 kd_status kd_knn_noalloc(kd_tree t, const float* queries, int64_t Q, int k, float maxRadius,
                          int32_t* out_idx, float* out_d2, kd_stream stream);
 
+/* ---------------------------------------------------------- range queries */
+
+/* All points within a radius of each query (Sec. 3: the same stack-free
+ * traversal, un-ordered: children are taken left then right, each entered
+ * only when the query ball reaches its side of the split plane).
+ *   queries   : device float32 [Q][dim];  0 <= Q < 2^31.
+ *   maxRadius : >= 0 or +inf (NaN or negative -> KD_EINVAL); a point is in
+ *               range when its binary32 squared distance (summed left to
+ *               right, no contraction) is <= fl32(maxRadius^2), as kd_knn.
+ *   cap       : 0..KD_MAX_K results kept per query.
+ *   out_count : device uint32 [Q]: the number of points in range.
+ *   out_idx   : device int32 [Q][cap] (may be NULL when cap = 0): the cap
+ *               nearest points in range, ascending by (d2, caller index),
+ *               i.e. exactly kd_knn(k = cap, maxRadius)'s rows; -1 after
+ *               the last.
+ *   out_d2    : device float32 [Q][cap] or NULL; +inf after the last.
+ * An empty tree gives counts 0.  A NaN query has no point in range.
+ * Scratch: the per-stream workspace of the kd_knn family (query records and
+ * sort buffers, kd_workspace_size(Q)).  Asynchronous on `stream`. */
+kd_status kd_radius_search(kd_tree t, const float* queries, int64_t Q, float maxRadius, int cap,
+                           int32_t* out_idx, float* out_d2, uint32_t* out_count, kd_stream stream);
+
+/* All points inside axis-aligned boxes (the un-ordered traversal of Sec. 3,
+ * each child entered only when the box reaches its side of the split plane).
+ *   boxes     : device float32 [Q][2][dim]: low corner then high corner; a
+ *               point p is inside when lo[j] <= p[j] <= hi[j] for every j
+ *               (inclusive; a box with lo[j] > hi[j] or a NaN bound holds
+ *               nothing).
+ *   cap       : 0..KD_MAX_K;  out_idx : device int32 [Q][cap]: the cap
+ *               smallest caller indices inside, ascending, -1 after the last.
+ *   out_count : device uint32 [Q]: the number of points inside.
+ * Boxes are processed in caller order.  Asynchronous on `stream`. */
+kd_status kd_box_search(kd_tree t, const float* boxes, int64_t Q, int cap, int32_t* out_idx,
+                        uint32_t* out_count, kd_stream stream);
+
 /* ------------------------------------------------- learned initial radius */
 
 /* A small MLP (3 -> 64 -> 64 -> 1, ReLU; bfloat16 operands, float32

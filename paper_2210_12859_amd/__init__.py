@@ -74,6 +74,8 @@ def lib():
         "kd_knn": ([P, P, i64, i32, f32, P, P, P], i32),
         "kd_knn_ex": ([P, P, i64, i32, f32, P, P, P, P, P], i32),
         "kd_knn_noalloc": ([P, P, i64, i32, f32, P, P, P], i32),
+        "kd_radius_search": ([P, P, i64, f32, i32, P, P, P, P], i32),
+        "kd_box_search": ([P, P, i64, i32, P, P, P], i32),
         "kd_radius_model_train": ([P, P, i64, i32, P, P, P], i32),
         "kd_knn_learned": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
         "kd_knn_with_radius": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
@@ -265,6 +267,40 @@ def kd_knn_noalloc(tree: Tree, queries, k, max_radius=math.inf, out_idx=None, ou
     _check(lib().kd_knn_noalloc(tree.handle, _ptr(queries), queries.shape[0], int(k), float(max_radius),
                                 _ptr(out_idx), _ptr(out_d2), _stream_handle(stream)))
     return out_idx, out_d2
+
+
+def kd_radius_search(tree: Tree, queries, max_radius, cap=0, want_d2=True, stream=None):
+    """Points within max_radius of each query: (count uint32 [Q], idx int32
+    [Q][cap], d2 float32 [Q][cap]); idx/d2 are None when cap is 0."""
+    import torch
+    _require(queries, torch.float32, "queries")
+    Q = queries.shape[0]
+    count = torch.empty(Q, dtype=torch.int32, device=queries.device)
+    idx = d2 = None
+    if cap > 0:
+        idx = torch.empty((Q, cap), dtype=torch.int32, device=queries.device)
+        if want_d2:
+            d2 = torch.empty((Q, cap), dtype=torch.float32, device=queries.device)
+    _check(lib().kd_radius_search(tree.handle, _ptr(queries), Q, float(max_radius), int(cap), _ptr(idx),
+                                  _ptr(d2), _ptr(count), _stream_handle(stream)))
+    return count, idx, d2
+
+
+def kd_box_search(tree: Tree, lo, hi, cap=0, stream=None):
+    """Points inside the boxes [lo, hi] (inclusive): (count uint32 [Q], idx
+    int32 [Q][cap] or None when cap is 0)."""
+    import torch
+    _require(lo, torch.float32, "lo")
+    _require(hi, torch.float32, "hi")
+    if lo.shape != hi.shape:
+        raise ValueError("lo and hi must have the same shape")
+    boxes = torch.stack([lo, hi], dim=1).contiguous()  # [Q][2][dim]
+    Q = lo.shape[0]
+    count = torch.empty(Q, dtype=torch.int32, device=lo.device)
+    idx = torch.empty((Q, cap), dtype=torch.int32, device=lo.device) if cap > 0 else None
+    _check(lib().kd_box_search(tree.handle, _ptr(boxes), Q, int(cap), _ptr(idx), _ptr(count),
+                               _stream_handle(stream)))
+    return count, idx
 
 
 def kd_knn_ex(tree: Tree, queries, k, max_radius=math.inf, out_idx=None, out_d2=None, visited=None,

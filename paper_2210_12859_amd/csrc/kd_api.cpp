@@ -456,6 +456,48 @@ kd_status kd_knn_ex(kd_tree t, const float* queries, int64_t Q, int k, float max
     return knn_entry(t, queries, Q, k, maxRadius, out_idx, out_d2, visited, opts, stream, "kd_knn_ex");
 }
 
+namespace {
+kd_status range_entry(kd_tree t, const float* in, int64_t Q, bool box, float maxRadius, int cap, int32_t* out_idx,
+                      float* out_d2, uint32_t* out_count, kd_stream stream, const char* fn) {
+    std::string f(fn);
+    if (Q < 0 || Q >= (int64_t(1) << 31)) return set_error(KD_EINVAL, f + ": Q out of range [0, 2^31)");
+    if (cap < 0 || cap > KD_MAX_K) return set_error(KD_EINVAL, f + ": cap out of range [0, 64]");
+    if (!box && (std::isnan(maxRadius) || maxRadius < 0.0f))
+        return set_error(KD_EINVAL, f + ": maxRadius must be >= 0 or +inf");
+    if (!t) return set_error(KD_EINVAL, f + ": tree is NULL");
+    if (Q > 0 && !in) return set_error(KD_EINVAL, f + (box ? ": boxes is NULL" : ": queries is NULL"));
+    if (Q > 0 && !out_count) return set_error(KD_EINVAL, f + ": out_count is NULL");
+    if (Q > 0 && cap > 0 && !out_idx) return set_error(KD_EINVAL, f + ": out_idx is NULL");
+    if (Q == 0) return KD_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (t->N == 0) {
+        hipLaunchKernelGGL(fill_zero_u32, dim3(unsigned((Q + 255) / 256)), dim3(256), 0, st, out_count, Q);
+        KD_HIP(hipGetLastError());
+        if (cap > 0) {
+            const int64_t n = Q * cap;
+            hipLaunchKernelGGL(fill_empty, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, out_idx,
+                               box ? nullptr : out_d2, n);
+            KD_HIP(hipGetLastError());
+        }
+        return KD_OK;
+    }
+    const float R2 = box ? 0.0f : maxRadius * maxRadius;  // binary32 product; +inf stays +inf
+    return run_range(t, in, Q, box, R2, cap, cap > 0 ? out_idx : nullptr, box || cap == 0 ? nullptr : out_d2,
+                     out_count, stream);
+}
+}  // namespace
+
+kd_status kd_radius_search(kd_tree t, const float* queries, int64_t Q, float maxRadius, int cap, int32_t* out_idx,
+                           float* out_d2, uint32_t* out_count, kd_stream stream) {
+    return range_entry(t, queries, Q, false, maxRadius, cap, out_idx, out_d2, out_count, stream,
+                       "kd_radius_search");
+}
+
+kd_status kd_box_search(kd_tree t, const float* boxes, int64_t Q, int cap, int32_t* out_idx, uint32_t* out_count,
+                        kd_stream stream) {
+    return range_entry(t, boxes, Q, true, 0.0f, cap, out_idx, nullptr, out_count, stream, "kd_box_search");
+}
+
 const char* kd_status_str(kd_status s) {
     switch (s) {
         case KD_OK: return "KD_OK";

@@ -1748,4 +1748,300 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
     return KD_OK;
 }
 
+// ------------------------------------------------------------ range queries
+//
+// All points within a radius of a query, or inside an axis-aligned box: the
+// un-ordered form of the same state machine (Sec. 3 calls it a trivial
+// simplification): children in fixed order, left then right, each entered
+// only when the query region can reach its half-space.  The left subtree of a
+// node holds coordinates <= its split value s in the split dimension, the
+// right subtree coordinates >= s, so
+//   radius (R2 = fl(r^2)): left is skipped iff sd = q[dim] - s > 0 and
+//     fl(sd^2) > R2 (every left point then has d2 >= fl(sd^2) > R2), and
+//     symmetrically for the right;
+//   box [lo, hi]: left is skipped iff lo[dim] > s, right iff hi[dim] < s.
+// Every point in the region is therefore processed, exactly once.  A lane
+// counts them and keeps the `cap` best in a sorted list: by (d2, index) for
+// radius queries (the kd_knn result within the radius), by caller index for
+// box queries.  One "return to parent" level is fused as in the kNN step: a
+// lane leaving a left child decides its parent's right child from the split
+// stored in the child's record.
+namespace {
+
+struct RangeArgs {
+    const void* nodes;      // TreeRec<D>[N + 2]
+    int32_t N;
+    const void* recs;       // radius: NodeRec<D>[Q] Morton-sorted; box: caller float [Q][2][D]
+    uint32_t Q;
+    float R2;               // radius queries
+    int cap;                // results kept per query (0..K)
+    int32_t* out_idx;       // [Q][cap] caller order
+    float* out_d2;          // radius: [Q][cap] or NULL
+    uint32_t* out_count;    // [Q]
+    uint32_t* counter;      // chunk cursor, zero at launch
+};
+
+template <int D, int K, bool BOXQ>
+struct RangeLane {
+    float a[D];        // radius: the query point; box: low corner
+    float b[BOXQ ? D : 1];  // box: high corner
+    uint64_t L[K];
+    int32_t curr, prev, row;
+    uint32_t count;
+};
+
+template <int D, int K, bool BOXQ>
+__device__ __forceinline__ void range_finish(const RangeLane<D, K, BOXQ>& s, const RangeArgs& a) {
+    a.out_count[s.row] = s.count;
+    if (a.cap == 0) return;
+    int32_t* oi = a.out_idx + int64_t(s.row) * a.cap;
+    float* od = (!BOXQ && a.out_d2) ? a.out_d2 + int64_t(s.row) * a.cap : nullptr;
+    const int off = K - a.cap;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (j >= off) {
+            const uint32_t id = uint32_t(s.L[j]);
+            const bool empty = id == SENT_IDX;
+            oi[j - off] = empty ? -1 : int32_t(id);
+            if (od) od[j - off] = empty ? __builtin_inff() : key_d2(s.L[j]);
+        }
+    }
+}
+
+// Which children the query region reaches, at a node of split dimension sel
+// with split value sv.
+template <int D, int K, bool BOXQ>
+__device__ __forceinline__ void range_wants(const RangeLane<D, K, BOXQ>& s, const DimSel<D>& sel, int rot, float sv,
+                                            float R2, bool& want_l, bool& want_r) {
+    if constexpr (BOXQ) {
+        const float lo = rot == 0 ? sel.template rot<0>(s.a) : sel.template rot<1>(s.a);
+        const float hi = rot == 0 ? sel.template rot<0>(s.b) : sel.template rot<1>(s.b);
+        want_l = lo <= sv;
+        want_r = hi >= sv;
+    } else {
+        const float qd = rot == 0 ? sel.template rot<0>(s.a) : sel.template rot<1>(s.a);
+        const float sd = qd - sv;
+        const bool far = sd * sd > R2;
+        want_l = !(sd > 0.0f && far);
+        want_r = !(sd < 0.0f && far);
+    }
+}
+
+template <int D, int K, bool BOXQ>
+__global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
+    const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);
+    const int32_t* __restrict__ ids = node_ids<D>(g1, a.N);
+    const uint32_t lane = __lane_id();
+    const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
+    // chunk of 64 query slots held across the wave (lane l: slot cb + l)
+    float ca[D], cbx[BOXQ ? D : 1];
+    int32_t crow = 0;
+    uint32_t cb = 0, cn = 0, cpos = 0;
+    bool exhausted = false;
+    RangeLane<D, K, BOXQ> s;
+    s.curr = 0;
+    for (;;) {
+        const uint64_t need = wave_ballot(s.curr == 0);
+        if (need && !exhausted) {
+            if (cpos == cn) {
+                uint32_t c = 0;
+                if (lane == 0) c = atomicAdd(a.counter, 64u);
+                c = __builtin_amdgcn_readfirstlane(c);
+                if (c >= a.Q) {
+                    exhausted = true;
+                } else {
+                    cb = c;
+                    cn = a.Q - c < 64u ? a.Q - c : 64u;
+                    cpos = 0;
+                    if (lane < cn) {
+                        const uint32_t slot = cb + lane;
+                        if constexpr (BOXQ) {
+                            const float* bx = static_cast<const float*>(a.recs) + size_t(slot) * 2 * D;
+#pragma unroll
+                            for (int j = 0; j < D; ++j) {
+                                ca[j] = bx[j];
+                                cbx[j] = bx[D + j];
+                            }
+                            crow = int32_t(slot);
+                        } else {
+                            const NodeRec<D> r = static_cast<const NodeRec<D>*>(a.recs)[slot];
+#pragma unroll
+                            for (int j = 0; j < D; ++j) ca[j] = r.c[j];
+                            crow = r.idx;
+                        }
+                    }
+                }
+            }
+            if (!exhausted) {
+                const uint32_t n = __popcll(need);
+                const uint32_t rank = __popcll(need & lt_mask);
+                const uint32_t take = n < cn - cpos ? n : cn - cpos;
+                const int src = int(cpos + (rank < take ? rank : 0));
+                float va[D], vb[BOXQ ? D : 1];
+#pragma unroll
+                for (int j = 0; j < D; ++j) va[j] = __shfl(ca[j], src);
+                if constexpr (BOXQ) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) vb[j] = __shfl(cbx[j], src);
+                }
+                const int32_t vrow = __shfl(crow, src);
+                if (s.curr == 0 && rank < take) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) s.a[j] = va[j];
+                    if constexpr (BOXQ) {
+#pragma unroll
+                        for (int j = 0; j < D; ++j) s.b[j] = vb[j];
+                    }
+                    s.row = vrow;
+                    s.count = 0;
+                    // spare slots (beyond cap) hold key 0 in front; empty
+                    // slots the largest key of the list's kind
+                    const uint64_t empty = BOXQ ? ((uint64_t(2) << 32) | SENT_IDX) : make_key(a.R2, SENT_IDX);
+#pragma unroll
+                    for (int j = 0; j < K; ++j) s.L[j] = (j < K - a.cap) ? uint64_t(0) : empty;
+                    s.curr = 1;
+                    s.prev = 0;
+                }
+                cpos += take;
+            }
+        }
+        if (!wave_any(s.curr != 0)) break;
+        if (s.curr != 0) {
+            const int32_t curr = s.curr;
+            float c[D];
+            int32_t idx;
+            float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
+            load_tree<D>(g1 + curr, c, idx, anc);
+            const bool from_parent = s.prev < curr;
+            if (from_parent) {
+                bool in;
+                uint64_t key;
+                if constexpr (BOXQ) {
+                    in = true;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) in = in & (s.a[j] <= c[j]) & (c[j] <= s.b[j]);
+                    key = 0;
+                } else {
+                    float dx[D];
+#pragma unroll
+                    for (int j = 0; j < D; ++j) dx[j] = s.a[j] - c[j];
+                    float d2 = dx[0] * dx[0];
+#pragma unroll
+                    for (int j = 1; j < D; ++j) d2 = d2 + dx[j] * dx[j];
+                    in = d2 <= a.R2;
+                    key = uint64_t(__float_as_uint(d2)) << 32;
+                }
+                if (in) {
+                    ++s.count;
+                    const int32_t id = rec_has_idx(D) ? idx : ids[curr];
+                    key |= uint32_t(id);
+                    if (BOXQ) key |= uint64_t(1) << 32;  // above the spare slots' key 0
+                    if (key < s.L[K - 1]) list_insert<K>(s.L, key);
+                }
+            }
+            const DimSel<D> sel(curr);
+            bool want_l, want_r;
+            range_wants<D, K, BOXQ>(s, sel, 0, sel.template rot<0>(c), a.R2, want_l, want_r);
+            const int32_t lc = curr << 1, rc = lc | 1;
+            int32_t next, nprev = curr;
+            if (from_parent && want_l && lc <= a.N) next = lc;
+            else if ((from_parent || s.prev == lc) && want_r && rc <= a.N) next = rc;
+            else {
+                // return to the parent p; from a left child, p's right child
+                // is decided here from p's split (stored in this record)
+                const int32_t p = curr >> 1;
+                next = p;
+                if (p != 0 && (curr & 1) == 0) {
+                    bool pl, pr;
+                    range_wants<D, K, BOXQ>(s, sel, 1, anc[0], a.R2, pl, pr);
+                    if (pr && (curr | 1) <= a.N) {
+                        next = curr | 1;
+                        nprev = p;
+                    } else {
+                        nprev = curr;  // p is done: the next trip returns from p
+                        next = p;
+                    }
+                }
+                if (next == p) {
+                    // leave p: step to p's parent as coming back from p
+                    nprev = p;
+                    next = p >> 1;
+                    if (p == 0) next = 0;
+                }
+            }
+            s.prev = nprev;
+            s.curr = next;
+            if (next == 0) range_finish<D, K, BOXQ>(s, a);
+        }
+    }
+}
+
+template <int D, int K>
+hipError_t launch_range_k(const RangeArgs& a, bool box, int grid, hipStream_t st) {
+    if (box) hipLaunchKernelGGL((range_persistent<D, K, true>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((range_persistent<D, K, false>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_range(int K, const RangeArgs& a, bool box, int grid, hipStream_t st) {
+    switch (K) {
+        case 1: return launch_range_k<D, 1>(a, box, grid, st);
+        case 2: return launch_range_k<D, 2>(a, box, grid, st);
+        case 4: return launch_range_k<D, 4>(a, box, grid, st);
+        case 8: return launch_range_k<D, 8>(a, box, grid, st);
+        case 16: return launch_range_k<D, 16>(a, box, grid, st);
+        case 32: return launch_range_k<D, 32>(a, box, grid, st);
+        case 64: return launch_range_k<D, 64>(a, box, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+kd_status run_range(kd_tree t, const float* queries_or_boxes, int64_t Q, bool box, float R2, int cap,
+                    int32_t* out_idx, float* out_d2, uint32_t* out_count, kd_stream stream) {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const DeviceInfo& dev = device_info(t->device);
+    const int sort_bits = 16;
+    void* ws = nullptr;
+    kd_status s = scratch(stream, query_scratch_bytes(box ? 0 : Q, t->dim, !box, false, false), &ws);
+    if (s != KD_OK) return s;
+    char* base = static_cast<char*>(ws);
+    uint32_t* counter = reinterpret_cast<uint32_t*>(base);
+    const size_t cursor_bytes = size_t(MAX_GROUPS) * CURSOR_STRIDE * 4;
+    const size_t head = cursor_bytes + 4096;
+    const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
+    void* sq = base + head;
+    RangeArgs a = {};
+    if (!box) {
+        // radius queries in Morton order (the first sort kernel clears the counter)
+        s = reorder_queries(t, queries_or_boxes, Q, sort_bits, base + head + sq_bytes, sq, counter, 64, st);
+        if (s != KD_OK) return s;
+        a.recs = sq;
+    } else {
+        hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, counter, 64);
+        KD_HIP(hipGetLastError());
+        a.recs = queries_or_boxes;
+    }
+    a.nodes = t->d_nodes;
+    a.N = int32_t(t->N);
+    a.Q = uint32_t(Q);
+    a.R2 = R2;
+    a.cap = cap;
+    a.out_idx = out_idx;
+    a.out_d2 = out_d2;
+    a.out_count = out_count;
+    a.counter = counter;
+    const int K = cap > 0 ? k_template(cap) : 1;
+    int64_t grid = int64_t(dev.cus) * 6;  // 24 waves per CU
+    const int64_t need = (Q + 255) / 256;
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    hipError_t e = t->dim == 2 ? launch_range<2>(K, a, box, int(grid), st)
+                 : t->dim == 3 ? launch_range<3>(K, a, box, int(grid), st) : launch_range<4>(K, a, box, int(grid), st);
+    if (e != hipSuccess) return hip_error(e, "range query launch");
+    return KD_OK;
+}
+
 }  // namespace kd

@@ -1,0 +1,211 @@
+"""GPU parity of the range queries (radius and box search) against the
+oracle's plain definitions, through the C ABI.
+
+The traversal is the un-ordered form of the stack-free loop (Sec. 3): it
+must process every point inside the query region exactly once, so the bar is
+exact: counts equal, indices byte-identical and squared distances
+bit-identical, row by row.  Radius rows are also kd_knn's rows for
+k = cap within the same radius."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2210_12859_amd as kd  # noqa: E402
+from paper_2210_12859_amd import datagen  # noqa: E402
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(_dev())
+
+
+def _build(P):
+    print(f"[gpu] range: build N={P.shape[0]} D={P.shape[1]}", flush=True)
+    return kd.kd_build(_t(P))
+
+
+def _radius(tree, Qs, maxr, cap):
+    c, i, d = kd.kd_radius_search(tree, _t(Qs), maxr, cap)
+    torch.cuda.synchronize()
+    Q = Qs.shape[0]
+    return (c.cpu().numpy().astype(np.int64),
+            None if i is None else i.cpu().numpy().reshape(Q, cap),
+            None if d is None else d.cpu().numpy().reshape(Q, cap))
+
+
+def _box(tree, lo, hi, cap):
+    c, i = kd.kd_box_search(tree, _t(lo), _t(hi), cap)
+    torch.cuda.synchronize()
+    return c.cpu().numpy().astype(np.int64), None if i is None else i.cpu().numpy().reshape(lo.shape[0], cap)
+
+
+def _same_radius(got, want, cap, ctx):
+    gc, gi, gd = got
+    oc, oi, od = want
+    bad = np.nonzero(gc != oc)[0]
+    assert len(bad) == 0, f"{ctx}: counts differ at {bad[:5]} gpu={gc[bad[:3]]} oracle={oc[bad[:3]]}"
+    if cap:
+        bad = np.nonzero((gi != oi).any(axis=1))[0]
+        assert len(bad) == 0, f"{ctx}: idx differ at {bad[:5]} gpu={gi[bad[:1]]} oracle={oi[bad[:1]]}"
+        assert np.array_equal(gd.view(np.uint32), od.view(np.uint32)), f"{ctx}: d2 bits differ"
+
+
+def _same_box(got, want, cap, ctx):
+    gc, gi = got
+    oc, oi = want
+    bad = np.nonzero(gc != oc)[0]
+    assert len(bad) == 0, f"{ctx}: counts differ at {bad[:5]} gpu={gc[bad[:3]]} oracle={oc[bad[:3]]}"
+    if cap:
+        bad = np.nonzero((gi != oi).any(axis=1))[0]
+        assert len(bad) == 0, f"{ctx}: idx differ at {bad[:5]} gpu={gi[bad[:1]]} oracle={oi[bad[:1]]}"
+
+
+def _boxes(rng, Qs, D, scale):
+    """Boxes around the query points, per-dimension half-widths drawn up to
+    `scale` (several boxes empty, several holding hundreds of points)."""
+    h = rng.random((Qs.shape[0], D), dtype=np.float32) * np.float32(scale)
+    return (Qs - h).astype(np.float32), (Qs + h).astype(np.float32)
+
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+def test_radius_uniform(oracle_lib, D):
+    rng = np.random.default_rng(D)
+    N, Q = 40_000, 12_000
+    P = rng.random((N, D), dtype=np.float32)
+    Qs = rng.random((Q, D), dtype=np.float32)
+    tree = _build(P)
+    maxr = {2: 0.02, 3: 0.05, 4: 0.12}[D]  # about 50 points per ball
+    for cap in (0, 1, 7, 64):
+        print(f"[gpu] radius uniform D={D} cap={cap}", flush=True)
+        want = oracle_lib.radius(P, Qs, maxr, cap)
+        _same_radius(_radius(tree, Qs, maxr, cap), want, cap, f"D={D} cap={cap}")
+    # rows equal kd_knn's within the same radius
+    gi, gd = kd.kd_knn(tree, _t(Qs), 8, maxr)
+    _, ri, rd = _radius(tree, Qs, maxr, 8)
+    assert np.array_equal(ri, gi.cpu().numpy()) and np.array_equal(rd.view(np.uint32), gd.cpu().numpy().view(np.uint32))
+    tree.close()
+
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+def test_box_uniform(oracle_lib, D):
+    rng = np.random.default_rng(10 + D)
+    N, Q = 40_000, 12_000
+    P = rng.random((N, D), dtype=np.float32)
+    Qs = rng.random((Q, D), dtype=np.float32)
+    lo, hi = _boxes(rng, Qs, D, {2: 0.03, 3: 0.08, 4: 0.15}[D])
+    tree = _build(P)
+    for cap in (0, 1, 5, 64):
+        print(f"[gpu] box uniform D={D} cap={cap}", flush=True)
+        want = oracle_lib.box(P, lo, hi, cap)
+        _same_box(_box(tree, lo, hi, cap), want, cap, f"D={D} cap={cap}")
+    tree.close()
+
+
+def test_radius_ties_on_grid(oracle_lib):
+    """Points and queries on a 1/8 grid: many points lie exactly on the ball's
+    boundary (d2 == R2 is inside) and on split planes; the split values equal
+    query coordinates, so both sides of a plane are reachable."""
+    rng = np.random.default_rng(3)
+    P = (rng.integers(0, 9, (30_000, 3)) / 8).astype(np.float32)
+    Qs = (rng.integers(0, 9, (5_000, 3)) / 8).astype(np.float32)
+    tree = _build(P)
+    for maxr in (0.0, 0.125, 0.25, math.sqrt(2) * 0.125):
+        for cap in (0, 16, 64):
+            print(f"[gpu] radius grid maxr={maxr} cap={cap}", flush=True)
+            want = oracle_lib.radius(P, Qs, maxr, cap)
+            _same_radius(_radius(tree, Qs, maxr, cap), want, cap, f"grid maxr={maxr} cap={cap}")
+    tree.close()
+
+
+def test_box_ties_degenerate_and_invalid(oracle_lib):
+    """Boxes whose faces lie on point coordinates (inclusive), zero-width
+    boxes (a single coordinate value), inverted boxes and NaN bounds (empty)."""
+    rng = np.random.default_rng(4)
+    P = (rng.integers(0, 9, (30_000, 2)) / 8).astype(np.float32)
+    Q = 6_000
+    a = (rng.integers(0, 9, (Q, 2)) / 8).astype(np.float32)
+    b = (rng.integers(0, 9, (Q, 2)) / 8).astype(np.float32)
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    lo[:500] = hi[:500]                # zero-width boxes
+    lo[500:1000], hi[500:1000] = hi[500:1000] + 0.0625, lo[500:1000]  # inverted
+    lo[1000:1100, 0] = np.nan
+    hi[1100:1200, 1] = np.nan
+    tree = _build(P)
+    for cap in (0, 3, 64):
+        print(f"[gpu] box grid cap={cap}", flush=True)
+        want = oracle_lib.box(P, lo, hi, cap)
+        _same_box(_box(tree, lo, hi, cap), want, cap, f"grid boxes cap={cap}")
+    c, _ = _box(tree, lo[500:1200], hi[500:1200], 0)
+    assert not c.any()
+    tree.close()
+
+
+def test_radius_infinite_nan_and_small_trees(oracle_lib):
+    rng = np.random.default_rng(5)
+    for N in (1, 2, 3, 7, 64, 65, 1000):
+        P = rng.random((N, 3), dtype=np.float32)
+        Qs = rng.random((300, 3), dtype=np.float32)
+        Qs[7] = np.nan
+        Qs[8, 1] = np.nan
+        tree = _build(P)
+        for maxr, cap in ((math.inf, 64), (math.inf, 0), (0.3, 5), (0.0, 1)):
+            want = oracle_lib.radius(P, Qs, maxr, cap)
+            got = _radius(tree, Qs, maxr, cap)
+            _same_radius(got, want, cap, f"N={N} maxr={maxr} cap={cap}")
+            if maxr == math.inf:
+                assert (got[0][np.isfinite(Qs).all(axis=1)] == N).all()
+                assert got[0][7] == 0 and got[0][8] == 0
+        tree.close()
+
+
+def test_empty_inputs():
+    dev = _dev()
+    tree = kd.kd_build(torch.zeros((0, 3), dtype=torch.float32, device=dev))
+    q = torch.rand((100, 3), device=dev)
+    c, i, d = kd.kd_radius_search(tree, q, math.inf, 4)
+    bc, bi = kd.kd_box_search(tree, q - 1, q + 1, 4)
+    torch.cuda.synchronize()
+    assert (c == 0).all() and (i == -1).all() and torch.isinf(d).all()
+    assert (bc == 0).all() and (bi == -1).all()
+    tree.close()
+    tree = kd.kd_build(torch.rand((1000, 3), device=dev))
+    e = torch.zeros((0, 3), dtype=torch.float32, device=dev)
+    c, i, d = kd.kd_radius_search(tree, e, 0.1, 4)
+    bc, bi = kd.kd_box_search(tree, e, e, 4)
+    torch.cuda.synchronize()
+    assert c.numel() == 0 and i.numel() == 0 and bc.numel() == 0
+    tree.close()
+
+
+def test_radius_box_clustered_1m_sampled(oracle_lib):
+    """1M clustered points (the shape of the kNN workloads), 1M queries in one
+    launch each: counts and rows of 4,000 sampled queries against the
+    definitions, radius rows of every query against kd_knn."""
+    P, Qs = datagen.workload("gmm64-1m")
+    rng = np.random.default_rng(6)
+    tree = _build(P)
+    maxr, cap = 0.01, 16
+    print("[gpu] range gmm64-1m: radius and box over 1M queries", flush=True)
+    gc, gi, gd = _radius(tree, Qs, maxr, cap)
+    lo, hi = _boxes(rng, Qs, 3, 0.01)
+    bc, bi = _box(tree, lo, hi, cap)
+    ki, kd2 = kd.kd_knn(tree, _t(Qs), cap, maxr)
+    torch.cuda.synchronize()
+    assert np.array_equal(gi, ki.cpu().numpy()), "radius rows differ from kd_knn"
+    assert np.array_equal(gd.view(np.uint32), kd2.cpu().numpy().view(np.uint32))
+    rows = rng.choice(Qs.shape[0], 4000, replace=False)
+    print("[gpu] range gmm64-1m: oracle on 4000 sampled rows", flush=True)
+    oc, oi, od = oracle_lib.radius(P, Qs[rows], maxr, cap)
+    _same_radius((gc[rows], gi[rows], gd[rows]), (oc, oi, od), cap, "gmm64 radius")
+    oc, oi = oracle_lib.box(P, lo[rows], hi[rows], cap)
+    _same_box((bc[rows], bi[rows]), (oc, oi), cap, "gmm64 box")
+    assert gc.sum() > 10 * Qs.shape[0] and bc.sum() > Qs.shape[0]  # non-trivial regions
+    tree.close()
