@@ -358,6 +358,89 @@ def paper_grid(args):
                       "note": "paper_qps: the paper's Table 1, RTX 3090 Ti; context only"}), flush=True)
 
 
+def range_queries(args):
+    """Radius and box search (the un-ordered traversal) on the 1M-point 3-D
+    workloads: regions sized for a mean of 8 and 64 points, results kept for
+    the 8 nearest / smallest indices or counts only.  Per cell: queries/s of
+    one call (Morton reorder + traversal), the traversal kernel's average
+    duration from the library's events on the call's stream, entered nodes
+    per query, the HBM roofline fraction of the entered nodes' coordinates,
+    and exactness of 256 sampled rows against the oracle's definitions."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2210_12859_amd as kd
+    from paper_2210_12859_amd import datagen
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    cells = []
+    for wl in ("uniform-1m", "gmm64-1m"):
+        P, Qs = datagen.workload(wl)
+        N, D = P.shape
+        Q = Qs.shape[0]
+        tree = kd.kd_build(torch.from_numpy(P).to(dev))
+        q = torch.from_numpy(Qs).to(dev)
+        rows = np.random.default_rng(0).choice(Q, 256, replace=False)
+        r_t = torch.from_numpy(rows).to(dev)
+        vis = torch.empty(Q, dtype=torch.int32, device=dev)
+        for kind, m, cap in (("radius", 8, 8), ("radius", 64, 0), ("box", 8, 8), ("box", 64, 0)):
+            if kind == "radius":
+                size = (3.0 * m / (4.0 * math.pi * N)) ** (1.0 / 3.0)
+                call = lambda v=None: kd.kd_radius_search(tree, q, size, cap, visited=v)
+            else:
+                size = 0.5 * (m / N) ** (1.0 / 3.0)  # half-width of a cube holding m points on average
+                lo_np = Qs - np.float32(size)
+                hi_np = Qs + np.float32(size)
+                lo = torch.from_numpy(lo_np).to(dev)
+                hi = torch.from_numpy(hi_np).to(dev)
+                call = lambda v=None: kd.kd_box_search(tree, lo, hi, cap, visited=v)
+            res = call(vis)
+            torch.cuda.synchronize()
+            entered = int(vis.to(torch.int64).sum().item())
+            cnt = res[0][r_t].cpu().numpy().astype(np.int64)
+            idx = res[1][r_t].cpu().numpy() if cap else None
+            if kind == "radius":
+                oc, oi, od = oracle.radius(P, Qs[rows], size, cap)
+                ok = bool(np.array_equal(cnt, oc) and (not cap or (
+                    np.array_equal(idx, oi) and np.array_equal(res[2][r_t].cpu().numpy().view(np.uint32),
+                                                               od.view(np.uint32)))))
+            else:
+                oc, oi = oracle.box(P, lo_np[rows], hi_np[rows], cap)
+                ok = bool(np.array_equal(cnt, oc) and (not cap or np.array_equal(idx, oi)))
+            mean_count = float(res[0].to(torch.float64).mean().item())
+            for _ in range(args.warmup):
+                call()
+            torch.cuda.synchronize()
+            kd.kd_timing_enable(True)
+            kd.kd_timing_collect(kind)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            kt, kn = kd.kd_timing_collect(kind)
+            kd.kd_timing_enable(False)
+            kern_ms = kt / max(1, kn)
+            alg = entered * D * 4
+            gbs = alg / (kern_ms / 1e3) / 1e9
+            cell = {"workload": wl, "kind": kind, "size": size, "cap": cap, "mean_count": mean_count,
+                    "qps": Q / (ms / 1e3), "ms_per_call": ms, "kernel_ms": kern_ms,
+                    "entered_per_query": entered / Q, "alg_bytes_per_launch": alg,
+                    "roofline_frac": gbs / HBM_PEAK_GBPS, "exact_on_sample": ok}
+            log(f"{wl} {kind} size={size:.4g} cap={cap}: {cell['qps'] / 1e6:.1f} M q/s, kernel {kern_ms:.3f} ms, "
+                f"{mean_count:.1f} in range, entered {entered / Q:.1f}/query, frac {cell['roofline_frac']:.3f}, "
+                f"exact {ok}")
+            cells.append(cell)
+        tree.close()
+    print(json.dumps({"range_queries": cells, "steps": args.steps, "warmup": args.warmup,
+                      "note": "radius: ball of radius size; box: cube of half-width size around each query"}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -377,7 +460,12 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--paper-grid", action="store_true",
                     help="only run the shape of the paper's Table 1 (4-D, N 1K..200M, 10M queries)")
+    ap.add_argument("--range", action="store_true",
+                    help="only run the radius and box search measurement (1M-point 3-D workloads)")
     args = ap.parse_args()
+    if args.range:
+        range_queries(args)
+        return
     if args.copy_calibration:
         copy_calibration()
         return

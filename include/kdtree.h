@@ -217,11 +217,15 @@ kd_status kd_knn_noalloc(kd_tree t, const float* queries, int64_t Q, int k, floa
  *               i.e. exactly kd_knn(k = cap, maxRadius)'s rows; -1 after
  *               the last.
  *   out_d2    : device float32 [Q][cap] or NULL; +inf after the last.
+ *   visited   : device uint32 [Q] or NULL: nodes the traversal entered
+ *               (first visits, each processed once).
  * An empty tree gives counts 0.  A NaN query has no point in range.
  * Scratch: the per-stream workspace of the kd_knn family (query records and
- * sort buffers, kd_workspace_size(Q)).  Asynchronous on `stream`. */
+ * sort buffers, kd_workspace_size(Q)); queries are taken in Morton order.
+ * Asynchronous on `stream`. */
 kd_status kd_radius_search(kd_tree t, const float* queries, int64_t Q, float maxRadius, int cap,
-                           int32_t* out_idx, float* out_d2, uint32_t* out_count, kd_stream stream);
+                           int32_t* out_idx, float* out_d2, uint32_t* out_count, uint32_t* visited,
+                           kd_stream stream);
 
 /* All points inside axis-aligned boxes (the un-ordered traversal of Sec. 3,
  * each child entered only when the box reaches its side of the split plane).
@@ -232,9 +236,11 @@ kd_status kd_radius_search(kd_tree t, const float* queries, int64_t Q, float max
  *   cap       : 0..KD_MAX_K;  out_idx : device int32 [Q][cap]: the cap
  *               smallest caller indices inside, ascending, -1 after the last.
  *   out_count : device uint32 [Q]: the number of points inside.
- * Boxes are processed in caller order.  Asynchronous on `stream`. */
+ *   visited   : device uint32 [Q] or NULL, as kd_radius_search.
+ * Boxes are taken in the Morton order of their centres (the per-stream
+ * workspace holds the centres too).  Asynchronous on `stream`. */
 kd_status kd_box_search(kd_tree t, const float* boxes, int64_t Q, int cap, int32_t* out_idx,
-                        uint32_t* out_count, kd_stream stream);
+                        uint32_t* out_count, uint32_t* visited, kd_stream stream);
 
 /* ------------------------------------------------- learned initial radius */
 

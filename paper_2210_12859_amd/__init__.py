@@ -74,8 +74,8 @@ def lib():
         "kd_knn": ([P, P, i64, i32, f32, P, P, P], i32),
         "kd_knn_ex": ([P, P, i64, i32, f32, P, P, P, P, P], i32),
         "kd_knn_noalloc": ([P, P, i64, i32, f32, P, P, P], i32),
-        "kd_radius_search": ([P, P, i64, f32, i32, P, P, P, P], i32),
-        "kd_box_search": ([P, P, i64, i32, P, P, P], i32),
+        "kd_radius_search": ([P, P, i64, f32, i32, P, P, P, P, P], i32),
+        "kd_box_search": ([P, P, i64, i32, P, P, P, P], i32),
         "kd_radius_model_train": ([P, P, i64, i32, P, P, P], i32),
         "kd_knn_learned": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
         "kd_knn_with_radius": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
@@ -269,9 +269,11 @@ def kd_knn_noalloc(tree: Tree, queries, k, max_radius=math.inf, out_idx=None, ou
     return out_idx, out_d2
 
 
-def kd_radius_search(tree: Tree, queries, max_radius, cap=0, want_d2=True, stream=None):
-    """Points within max_radius of each query: (count uint32 [Q], idx int32
-    [Q][cap], d2 float32 [Q][cap]); idx/d2 are None when cap is 0."""
+def kd_radius_search(tree: Tree, queries, max_radius, cap=0, want_d2=True, visited=None, stream=None):
+    """Points within max_radius of each query: (count [Q], idx int32 [Q][cap],
+    d2 float32 [Q][cap]); idx/d2 are None when cap is 0.  Counts come back
+    in an int32 tensor (the library writes uint32; counts stay below 2^30).
+    visited: optional int32 [Q] tensor receiving the entered-node counts."""
     import torch
     _require(queries, torch.float32, "queries")
     Q = queries.shape[0]
@@ -281,14 +283,16 @@ def kd_radius_search(tree: Tree, queries, max_radius, cap=0, want_d2=True, strea
         idx = torch.empty((Q, cap), dtype=torch.int32, device=queries.device)
         if want_d2:
             d2 = torch.empty((Q, cap), dtype=torch.float32, device=queries.device)
+    if visited is not None:
+        _require(visited, torch.int32, "visited", (Q,))
     _check(lib().kd_radius_search(tree.handle, _ptr(queries), Q, float(max_radius), int(cap), _ptr(idx),
-                                  _ptr(d2), _ptr(count), _stream_handle(stream)))
+                                  _ptr(d2), _ptr(count), _ptr(visited), _stream_handle(stream)))
     return count, idx, d2
 
 
-def kd_box_search(tree: Tree, lo, hi, cap=0, stream=None):
-    """Points inside the boxes [lo, hi] (inclusive): (count uint32 [Q], idx
-    int32 [Q][cap] or None when cap is 0)."""
+def kd_box_search(tree: Tree, lo, hi, cap=0, visited=None, stream=None):
+    """Points inside the boxes [lo, hi] (inclusive): (count [Q], idx int32
+    [Q][cap] or None when cap is 0); visited as kd_radius_search."""
     import torch
     _require(lo, torch.float32, "lo")
     _require(hi, torch.float32, "hi")
@@ -298,7 +302,9 @@ def kd_box_search(tree: Tree, lo, hi, cap=0, stream=None):
     Q = lo.shape[0]
     count = torch.empty(Q, dtype=torch.int32, device=lo.device)
     idx = torch.empty((Q, cap), dtype=torch.int32, device=lo.device) if cap > 0 else None
-    _check(lib().kd_box_search(tree.handle, _ptr(boxes), Q, int(cap), _ptr(idx), _ptr(count),
+    if visited is not None:
+        _require(visited, torch.int32, "visited", (Q,))
+    _check(lib().kd_box_search(tree.handle, _ptr(boxes), Q, int(cap), _ptr(idx), _ptr(count), _ptr(visited),
                                _stream_handle(stream)))
     return count, idx
 

@@ -1771,13 +1771,15 @@ namespace {
 struct RangeArgs {
     const void* nodes;      // TreeRec<D>[N + 2]
     int32_t N;
-    const void* recs;       // radius: NodeRec<D>[Q] Morton-sorted; box: caller float [Q][2][D]
+    const void* recs;       // NodeRec<D>[Q] Morton-sorted: the query point (radius) or the box centre
+    const float* boxes;     // box queries: caller float [Q][2][D]
     uint32_t Q;
     float R2;               // radius queries
     int cap;                // results kept per query (0..K)
     int32_t* out_idx;       // [Q][cap] caller order
     float* out_d2;          // radius: [Q][cap] or NULL
     uint32_t* out_count;    // [Q]
+    uint32_t* visited;      // [Q] entered nodes, or NULL
     uint32_t* counter;      // chunk cursor, zero at launch
 };
 
@@ -1787,12 +1789,13 @@ struct RangeLane {
     float b[BOXQ ? D : 1];  // box: high corner
     uint64_t L[K];
     int32_t curr, prev, row;
-    uint32_t count;
+    uint32_t count, vis;
 };
 
 template <int D, int K, bool BOXQ>
 __device__ __forceinline__ void range_finish(const RangeLane<D, K, BOXQ>& s, const RangeArgs& a) {
     a.out_count[s.row] = s.count;
+    if (a.visited) a.visited[s.row] = s.vis;
     if (a.cap == 0) return;
     int32_t* oi = a.out_idx + int64_t(s.row) * a.cap;
     float* od = (!BOXQ && a.out_d2) ? a.out_d2 + int64_t(s.row) * a.cap : nullptr;
@@ -1854,20 +1857,18 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
                     cn = a.Q - c < 64u ? a.Q - c : 64u;
                     cpos = 0;
                     if (lane < cn) {
-                        const uint32_t slot = cb + lane;
+                        const NodeRec<D> r = load_query<D>(static_cast<const NodeRec<D>*>(a.recs) + cb + lane);
+                        crow = r.idx;
                         if constexpr (BOXQ) {
-                            const float* bx = static_cast<const float*>(a.recs) + size_t(slot) * 2 * D;
+                            const float* bx = a.boxes + size_t(crow) * 2 * D;
 #pragma unroll
                             for (int j = 0; j < D; ++j) {
                                 ca[j] = bx[j];
                                 cbx[j] = bx[D + j];
                             }
-                            crow = int32_t(slot);
                         } else {
-                            const NodeRec<D> r = static_cast<const NodeRec<D>*>(a.recs)[slot];
 #pragma unroll
                             for (int j = 0; j < D; ++j) ca[j] = r.c[j];
-                            crow = r.idx;
                         }
                     }
                 }
@@ -1894,6 +1895,7 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
                     }
                     s.row = vrow;
                     s.count = 0;
+                    s.vis = 0;
                     // spare slots (beyond cap) hold key 0 in front; empty
                     // slots the largest key of the list's kind
                     const uint64_t empty = BOXQ ? ((uint64_t(2) << 32) | SENT_IDX) : make_key(a.R2, SENT_IDX);
@@ -1914,6 +1916,7 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
             load_tree<D>(g1 + curr, c, idx, anc);
             const bool from_parent = s.prev < curr;
             if (from_parent) {
+                ++s.vis;
                 bool in;
                 uint64_t key;
                 if constexpr (BOXQ) {
@@ -1976,6 +1979,14 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
     }
 }
 
+// Centre of each box, (lo + hi) / 2 per dimension (the sort key only).
+__global__ void box_centres(const float* __restrict__ boxes, int64_t Q, int D, float* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= Q * D) return;
+    const int64_t q = i / D, j = i - q * D;
+    out[i] = boxes[q * 2 * D + j] * 0.5f + boxes[q * 2 * D + D + j] * 0.5f;
+}
+
 template <int D, int K>
 hipError_t launch_range_k(const RangeArgs& a, bool box, int grid, hipStream_t st) {
     if (box) hipLaunchKernelGGL((range_persistent<D, K, true>), dim3(grid), dim3(256), 0, st, a);
@@ -2000,12 +2011,15 @@ hipError_t launch_range(int K, const RangeArgs& a, bool box, int grid, hipStream
 }  // namespace
 
 kd_status run_range(kd_tree t, const float* queries_or_boxes, int64_t Q, bool box, float R2, int cap,
-                    int32_t* out_idx, float* out_d2, uint32_t* out_count, kd_stream stream) {
+                    int32_t* out_idx, float* out_d2, uint32_t* out_count, uint32_t* visited, kd_stream stream) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const DeviceInfo& dev = device_info(t->device);
     const int sort_bits = 16;
     void* ws = nullptr;
-    kd_status s = scratch(stream, query_scratch_bytes(box ? 0 : Q, t->dim, !box, false, false), &ws);
+    // scratch: [counter | ...] query records, sort buffers, box centres
+    const size_t qb = query_scratch_bytes(Q, t->dim, true, false, false);
+    const size_t centre_bytes = box ? (size_t(Q) * t->dim * 4 + 255) & ~size_t(255) : 0;
+    kd_status s = scratch(stream, qb + centre_bytes, &ws);
     if (s != KD_OK) return s;
     char* base = static_cast<char*>(ws);
     uint32_t* counter = reinterpret_cast<uint32_t*>(base);
@@ -2014,16 +2028,26 @@ kd_status run_range(kd_tree t, const float* queries_or_boxes, int64_t Q, bool bo
     const size_t sq_bytes = (size_t(Q) * rec_bytes(t->dim) + 255) & ~size_t(255);
     void* sq = base + head;
     RangeArgs a = {};
-    if (!box) {
-        // radius queries in Morton order (the first sort kernel clears the counter)
-        s = reorder_queries(t, queries_or_boxes, Q, sort_bits, base + head + sq_bytes, sq, counter, 64, st);
-        if (s != KD_OK) return s;
-        a.recs = sq;
-    } else {
-        hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, counter, 64);
+    const float* keys = queries_or_boxes;
+    if (box) {
+        // boxes are ordered by their centres
+        float* centres = reinterpret_cast<float*>(base + qb);
+        const int64_t n = Q * t->dim;
+        hipLaunchKernelGGL(box_centres, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, queries_or_boxes, Q,
+                           t->dim, centres);
         KD_HIP(hipGetLastError());
-        a.recs = queries_or_boxes;
+        keys = centres;
+        a.boxes = queries_or_boxes;
     }
+    // Morton order (the first sort kernel clears the counter)
+    hipEvent_t evs;
+    s = timing_begin(st, &evs);
+    if (s != KD_OK) return s;
+    s = reorder_queries(t, keys, Q, sort_bits, base + head + sq_bytes, sq, counter, 64, st);
+    if (s != KD_OK) return s;
+    s = timing_end(st, evs, "sort");
+    if (s != KD_OK) return s;
+    a.recs = sq;
     a.nodes = t->d_nodes;
     a.N = int32_t(t->N);
     a.Q = uint32_t(Q);
@@ -2032,16 +2056,20 @@ kd_status run_range(kd_tree t, const float* queries_or_boxes, int64_t Q, bool bo
     a.out_idx = out_idx;
     a.out_d2 = out_d2;
     a.out_count = out_count;
+    a.visited = visited;
     a.counter = counter;
     const int K = cap > 0 ? k_template(cap) : 1;
     int64_t grid = int64_t(dev.cus) * 6;  // 24 waves per CU
     const int64_t need = (Q + 255) / 256;
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
+    hipEvent_t ev0;
+    s = timing_begin(st, &ev0);
+    if (s != KD_OK) return s;
     hipError_t e = t->dim == 2 ? launch_range<2>(K, a, box, int(grid), st)
                  : t->dim == 3 ? launch_range<3>(K, a, box, int(grid), st) : launch_range<4>(K, a, box, int(grid), st);
     if (e != hipSuccess) return hip_error(e, "range query launch");
-    return KD_OK;
+    return timing_end(st, ev0, box ? "box" : "radius");
 }
 
 }  // namespace kd

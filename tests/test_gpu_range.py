@@ -166,6 +166,38 @@ def test_radius_infinite_nan_and_small_trees(oracle_lib):
         tree.close()
 
 
+def test_visited_counts_and_unbounded_regions(oracle_lib):
+    """Entered-node counts: every point in the region is entered, nothing is
+    entered twice, and an unbounded region (infinite radius, infinite box
+    faces) enters all N nodes."""
+    rng = np.random.default_rng(8)
+    N, Q = 20_000, 4_000
+    P = rng.random((N, 3), dtype=np.float32)
+    Qs = rng.random((Q, 3), dtype=np.float32)
+    tree = _build(P)
+    q = _t(Qs)
+    vis = torch.empty(Q, dtype=torch.int32, device=_dev())
+    for maxr in (0.03, math.inf):
+        c, _, _ = kd.kd_radius_search(tree, q, maxr, 0, visited=vis)
+        torch.cuda.synchronize()
+        c, v = c.cpu().numpy(), vis.cpu().numpy()
+        assert (v >= c).all() and (v <= N).all() and (v >= 1).all()
+        if maxr == math.inf:
+            assert (c == N).all() and (v == N).all()
+    lo, hi = _boxes(rng, Qs, 3, 0.05)
+    lo[:100] = -np.inf
+    hi[:100] = np.inf
+    hi[100:200, 2] = np.inf
+    c, _ = kd.kd_box_search(tree, _t(lo), _t(hi), 4, visited=vis)
+    torch.cuda.synchronize()
+    c, v = c.cpu().numpy(), vis.cpu().numpy()
+    assert (v >= c).all() and (v <= N).all()
+    assert (c[:100] == N).all() and (v[:100] == N).all()
+    oc, _ = oracle_lib.box(P, lo, hi, 0)
+    assert np.array_equal(c, oc)
+    tree.close()
+
+
 def test_empty_inputs():
     dev = _dev()
     tree = kd.kd_build(torch.zeros((0, 3), dtype=torch.float32, device=dev))
