@@ -2,10 +2,11 @@
 
   * ``brute_np``: the plain definition of the result with explicit float32
     elementwise operations (no reductions that could reassociate).
-  * ``stackfree_sequence``: the two-integer state machine of the paper's
-    Sec. 3.2 run on the CPU, recording the nodes it processes, to check the
-    paper's claim (Sec. 3.1) that it processes the same nodes in the same
-    order as the ordered recursion.
+  * ``ordered_walk``: the ordered traversal with an explicit stack, recording
+    the nodes it processes and the tour of node entries, to check the
+    oracle's recursion and the trip counts of a two-integer state machine
+    (Sec. 3.1: every move is to a child or to the parent, so the next node
+    follows from the current and the previous one).
   * ``eytzinger``: textbook breadth-first layout of a sorted array, filled by
     an in-order walk of the implicit complete binary tree.
 """
@@ -39,50 +40,56 @@ def brute_np(points, q, k, R2):
     return idx, d
 
 
-def stackfree_sequence(points, order, q, k, R2):
-    """Run the Sec. 3.2 state machine; processNode keeps a k-list of
-    (d2, idx) and the search radius is the list's worst d2.  Returns
-    (processed positions in order, loop iterations, idx list, d2 list)."""
+def ordered_walk(points, order, q, k, R2):
+    """The ordered traversal of Sec. 3.1 (node first, then the close child,
+    then the far child if its split plane is within the current search
+    radius) written with an explicit stack of frames, independently of the
+    oracle's recursion.  The close child is entered even when it does not
+    exist (an immediate return), the far child only when in range; a missing
+    node is entered and left at once.  Returns (processed positions in order,
+    the tour of entered positions -- every node as it is entered and again
+    each time a child returns to it --, idx list, d2 list).  The tour is the
+    sequence of `curr` values a two-integer state machine passes through: one
+    loop trip per entry."""
     P = np.asarray(points, np.float32)
     N, D = P.shape
     q = np.asarray(q, np.float32)
     lst = [(np.float32(R2), 2**31 - 1)] * k
-    seq = []
-    curr, prev = 0, -1
-    iters = 0
-    while True:
-        iters += 1
-        parent = (curr + 1) // 2 - 1
-        if curr >= N:
-            prev, curr = curr, parent
+    seq, tour = [], []
+    # frame: [position, stage]; stage 0 = entering, 1 = close child done,
+    # 2 = far child done (or skipped)
+    stack = [[0, 0]]
+    while stack:
+        fr = stack[-1]
+        pos = fr[0]
+        tour.append(pos)
+        if pos >= N:  # missing node: entered and left at once
+            stack.pop()
             continue
-        from_parent = prev < curr
-        p = P[order[curr]]
-        if from_parent:
-            seq.append(curr)
+        p = P[order[pos]]
+        dim = int(np.floor(np.log2(pos + 1))) % D
+        sd = np.float32(q[dim] - p[dim])
+        close = 2 * pos + (2 if sd > 0 else 1)
+        far = 2 * pos + (1 if sd > 0 else 2)
+        if fr[1] == 0:
+            seq.append(pos)
             dd = d2_np(p[None, :], q)[0]
-            key = (dd, int(order[curr]))
+            key = (dd, int(order[pos]))
             if key < lst[-1]:
                 lst = sorted(lst[:-1] + [key])
-        level = int(np.floor(np.log2(curr + 1)))
-        dim = level % D
-        sd = np.float32(q[dim] - p[dim])
-        close_side = 1 if sd > 0 else 0
-        close_c = 2 * curr + 1 + close_side
-        far_c = 2 * curr + 2 - close_side
-        far_in = np.float32(sd * sd) <= lst[-1][0]
-        if from_parent:
-            nxt = close_c
-        elif prev == close_c:
-            nxt = far_c if far_in else parent
+            fr[1] = 1
+            stack.append([close, 0])
+        elif fr[1] == 1:
+            fr[1] = 2
+            if np.float32(sd * sd) <= lst[-1][0]:
+                stack.append([far, 0])
+            else:
+                stack.pop()
         else:
-            nxt = parent
-        if nxt == -1:
-            break
-        prev, curr = curr, nxt
+            stack.pop()
     idx = np.array([i if i != 2**31 - 1 else -1 for _, i in lst], np.int32)
     d = np.array([dd if i != 2**31 - 1 else np.inf for dd, i in lst], np.float32)
-    return seq, iters, idx, d
+    return seq, tour, idx, d
 
 
 def eytzinger(sorted_ids):

@@ -234,6 +234,10 @@ def test_prefix_and_filter_properties(oracle_lib):
 @pytest.mark.parametrize("N,D,k", [(1, 2, 1), (6, 2, 2), (17, 3, 1), (100, 3, 4), (255, 2, 8),
                                    (256, 3, 8), (513, 4, 3)])
 def test_stackfree_processes_same_sequence(oracle_lib, N, D, k):
+    """The oracle's recursion processes the nodes of an independent
+    explicit-stack walk, in the same order, with the same result; the walk's
+    tour moves only between parent and child (what lets two integers carry
+    the state, Sec. 3.1), so consecutive entries determine each move."""
     rng = np.random.default_rng(N + 31 * D)
     P = rng.random((N, D), dtype=np.float32)
     order = oracle_lib.build_tree(P)
@@ -242,21 +246,29 @@ def test_stackfree_processes_same_sequence(oracle_lib, N, D, k):
         q = rng.random(D, dtype=np.float32)
         if t == 11:
             q = P[order[N // 2]].copy()
-        seq, _, sidx, sd = refimpl.stackfree_sequence(P, order, q, k, R2)
+        seq, tour, sidx, sd = refimpl.ordered_walk(P, order, q, k, R2)
         oi, od, vis, _, oseq = oracle_lib.knn_one(P, order, q, k, record_sequence=True)
         assert oseq.tolist() == seq
         assert vis == len(seq)
         assert oi.tolist() == sidx.tolist()
+        assert tour[0] == 0 and tour[-1] == 0
+        for a, b in zip(tour, tour[1:]):
+            assert b in (2 * a + 1, 2 * a + 2) or a in (2 * b + 1, 2 * b + 2), (a, b)
+        # every entry but the root's comes down one edge and goes back up it
+        entries = sum(1 for a, b in zip([-1] + tour, tour) if b > a)
+        assert len(tour) == 2 * entries - 1
 
 
 def test_figure1_stackfree_iterations():
+    """Loop trips of the two-integer traversal on the Figure 1 tree: one per
+    entry in the tour (9 for fcp at (9, 2), 15 for k = 2 at (3, 5))."""
     g = json.load(open(os.path.join(GOLDEN, "figure1.json")))
     P = np.array(g["points"], np.float32)
     order = np.array(g["order"], np.int32)
-    seq, iters, idx, _ = refimpl.stackfree_sequence(P, order, [9, 2], 1, np.float32(np.inf))
-    assert seq == [0, 2, 5] and iters == 9 and idx.tolist() == [4]
-    seq, iters, idx, _ = refimpl.stackfree_sequence(P, order, [3, 5], 2, np.float32(np.inf))
-    assert seq == [0, 1, 4, 3] and iters == 15 and idx.tolist() == [0, 1]
+    seq, tour, idx, _ = refimpl.ordered_walk(P, order, [9, 2], 1, np.float32(np.inf))
+    assert seq == [0, 2, 5] and len(tour) == 9 and idx.tolist() == [4]
+    seq, tour, idx, _ = refimpl.ordered_walk(P, order, [3, 5], 2, np.float32(np.inf))
+    assert seq == [0, 1, 4, 3] and len(tour) == 15 and idx.tolist() == [0, 1]
 
 
 # ------------------------------------------------------------ learned rule
