@@ -6,7 +6,8 @@ shares no code with the HIP path (``paper_2210_12859_amd``), and neither side
 imports the other.
 
 Contents
-  * ``kd_oracle.c`` (loaded through ctypes): canonical build, the ordered
+  * ``kd_oracle.c`` (loaded through ctypes): canonical build (split
+    dimension by level, or stored per node: the widest extent), the ordered
     recursive traversal of the paper's Sec. 3.1, brute force, the
     learned-radius rule, radius and box queries by their plain definitions
     (the "find all points within a radius / inside a box" variants of Sec. 3),
@@ -62,6 +63,12 @@ def _load():
     lib.oracle_left_size.restype = i64
     lib.oracle_build.argtypes = [P, i64, i32, P]
     lib.oracle_build.restype = i32
+    lib.oracle_build_rule.argtypes = [P, i64, i32, i32, P, P]
+    lib.oracle_build_rule.restype = i32
+    lib.oracle_knn_one_dims.argtypes = [P, P, P, i64, i32, P, i32, f32, P, P, P, P, i64]
+    lib.oracle_knn_one_dims.restype = i32
+    lib.oracle_knn_batch_dims.argtypes = [P, P, P, i64, i32, P, i64, i32, f32, P, P, P, i32]
+    lib.oracle_knn_batch_dims.restype = i32
     lib.oracle_knn_one.argtypes = [P, P, i64, i32, P, i32, f32, P, P, P, P, i64]
     lib.oracle_knn_one.restype = i32
     lib.oracle_worst0.argtypes = [f32, f32]
@@ -118,8 +125,26 @@ def build_tree(points) -> np.ndarray:
     return order
 
 
-def knn_one(points, order, q, k, max_radius=np.inf, worst0=None, record_sequence=False):
-    """One query.  Returns (idx[k], d2[k], visited, found[, sequence])."""
+def build_tree_widest(points):
+    """Tree with stored split dimensions, each node's the widest extent of its
+    point set.  Returns (order[N], dims[N] uint8), by level-order position."""
+    P = _f32c(points)
+    N, D = P.shape
+    order = np.empty(N, dtype=np.int32)
+    dims = np.empty(N, dtype=np.uint8)
+    rc = _load().oracle_build_rule(_ptr(P), N, D, 1, _ptr(order), _ptr(dims))
+    if rc != 0:
+        raise ValueError("oracle_build_rule failed")
+    return order, dims
+
+
+def _dims_arg(dims):
+    return None if dims is None else np.ascontiguousarray(dims, np.uint8)
+
+
+def knn_one(points, order, q, k, max_radius=np.inf, worst0=None, record_sequence=False, dims=None):
+    """One query (dims: stored split dimensions, else by level).
+    Returns (idx[k], d2[k], visited, found[, sequence])."""
     P = _f32c(points)
     N, D = P.shape
     q = _f32c(q).reshape(D)
@@ -129,16 +154,17 @@ def knn_one(points, order, q, k, max_radius=np.inf, worst0=None, record_sequence
     od = np.empty(k, np.float32)
     vis = np.zeros(1, np.int64)
     seq = np.full(max(N, 1), -1, np.int32) if record_sequence else None
-    found = _load().oracle_knn_one(_ptr(P), _ptr(np.ascontiguousarray(order, np.int32)), N, D,
-                                   _ptr(q), k, w0, _ptr(oi), _ptr(od), _ptr(vis),
-                                   _ptr(seq), len(seq) if seq is not None else 0)
+    found = _load().oracle_knn_one_dims(_ptr(P), _ptr(np.ascontiguousarray(order, np.int32)),
+                                        _ptr(_dims_arg(dims)), N, D, _ptr(q), k, w0, _ptr(oi), _ptr(od),
+                                        _ptr(vis), _ptr(seq), len(seq) if seq is not None else 0)
     if record_sequence:
         return oi, od, int(vis[0]), found, seq[: int(vis[0])].copy()
     return oi, od, int(vis[0]), found
 
 
-def knn(points, order, queries, k, max_radius=np.inf, nthreads=None):
-    """Batch of queries through the recursive traversal.
+def knn(points, order, queries, k, max_radius=np.inf, nthreads=None, dims=None):
+    """Batch of queries through the recursive traversal (dims: stored split
+    dimensions by position, else by level).
     Returns (idx[Q][k], d2[Q][k], visited[Q])."""
     P = _f32c(points)
     Qs = _f32c(queries)
@@ -147,9 +173,9 @@ def knn(points, order, queries, k, max_radius=np.inf, nthreads=None):
     oi = np.empty((Q, k), np.int32)
     od = np.empty((Q, k), np.float32)
     vis = np.empty(Q, np.int64)
-    rc = _load().oracle_knn_batch(_ptr(P), _ptr(np.ascontiguousarray(order, np.int32)), N, D,
-                                  _ptr(Qs), Q, k, sq_radius(max_radius), _ptr(oi), _ptr(od),
-                                  _ptr(vis), nthreads or default_threads())
+    rc = _load().oracle_knn_batch_dims(_ptr(P), _ptr(np.ascontiguousarray(order, np.int32)),
+                                       _ptr(_dims_arg(dims)), N, D, _ptr(Qs), Q, k, sq_radius(max_radius),
+                                       _ptr(oi), _ptr(od), _ptr(vis), nthreads or default_threads())
     if rc != 0:
         raise ValueError("oracle_knn_batch failed")
     return oi, od, vis

@@ -32,6 +32,13 @@
  *  - Learned-radius rule: start from worst0 = min(R2, fl(r0*r0)) (r0 finite
  *    and >= 0, else R2); if fewer than k points were found and worst0 < R2,
  *    run again from R2.
+ *  - Stored split dimensions (Sec. 3 leaves the split dimension to the
+ *    builder and lets a node carry it; Sec. 4 names node types that store
+ *    it): the "widest" rule picks, at each node, the dimension of largest
+ *    extent of the node's point set, extent_j = fl32(max_j - min_j), the
+ *    lowest j among equal extents; the rest of the build is unchanged (the
+ *    same ranks, ordered by (coordinate in that dimension, index)).  The
+ *    traversal then reads each node's dimension from dims[pos].
  */
 #include <math.h>
 #include <pthread.h>
@@ -98,29 +105,57 @@ static int cmp_by_dim(const void* a, const void* b) {
     return (ia > ib) - (ia < ib);
 }
 
-static void build_rec(const float* P, int64_t N, int D, int32_t* S, int64_t n,
-                      int64_t pos, int32_t* order) {
+/* Dimension of largest extent fl32(max - min) over the n >= 1 points S[0..n),
+ * the lowest dimension among equal extents. */
+static int widest_dim(const float* P, int D, const int32_t* S, int64_t n) {
+    int best = 0;
+    float best_ext = -1.0f;
+    for (int j = 0; j < D; ++j) {
+        float mn = P[(int64_t)S[0] * D + j], mx = mn;
+        for (int64_t i = 1; i < n; ++i) {
+            float v = P[(int64_t)S[i] * D + j];
+            if (v < mn) mn = v;
+            if (v > mx) mx = v;
+        }
+        float ext = mx - mn;
+        if (ext > best_ext) {
+            best_ext = ext;
+            best = j;
+        }
+    }
+    return best;
+}
+
+static void build_rec(const float* P, int64_t N, int D, int rule, int32_t* S, int64_t n,
+                      int64_t pos, int32_t* order, uint8_t* dims) {
     if (pos >= N) return; /* then n == 0 */
-    int dim = level_of(pos) % D;
+    int dim = rule == 1 ? widest_dim(P, D, S, n) : level_of(pos) % D;
+    if (dims) dims[pos] = (uint8_t)dim;
     g_sort.P = P; g_sort.D = D; g_sort.dim = dim;
     qsort(S, (size_t)n, sizeof(int32_t), cmp_by_dim);
     int64_t m = oracle_left_size(n);
     order[pos] = S[m];
-    build_rec(P, N, D, S, m, 2 * pos + 1, order);
-    build_rec(P, N, D, S + m + 1, n - m - 1, 2 * pos + 2, order);
+    build_rec(P, N, D, rule, S, m, 2 * pos + 1, order, dims);
+    build_rec(P, N, D, rule, S + m + 1, n - m - 1, 2 * pos + 2, order, dims);
 }
 
-/* order[pos] = caller index of the point stored at level-order position pos.
+/* order[pos] = caller index of the point stored at level-order position pos;
+ * dims[pos] (nullable) = its split dimension.  rule 0: floor(log2(pos+1))
+ * mod D; rule 1: the widest extent of the node's point set.
  * Returns 0, or -1 on bad arguments / allocation failure. */
-int oracle_build(const float* P, int64_t N, int D, int32_t* order) {
-    if (N < 0 || D < 1 || D > 8) return -1;
+int oracle_build_rule(const float* P, int64_t N, int D, int rule, int32_t* order, uint8_t* dims) {
+    if (N < 0 || D < 1 || D > 8 || rule < 0 || rule > 1) return -1;
     if (N == 0) return 0;
     int32_t* S = (int32_t*)malloc((size_t)N * sizeof(int32_t));
     if (!S) return -1;
     for (int64_t i = 0; i < N; ++i) S[i] = (int32_t)i;
-    build_rec(P, N, D, S, N, 0, order);
+    build_rec(P, N, D, rule, S, N, 0, order, dims);
     free(S);
     return 0;
+}
+
+int oracle_build(const float* P, int64_t N, int D, int32_t* order) {
+    return oracle_build_rule(P, N, D, 0, order, NULL);
 }
 
 /* ------------------------------------------------------------------ query */
@@ -137,6 +172,7 @@ typedef struct {
     int64_t visited; /* processed nodes (first visits of existing nodes) */
     int32_t* seq;    /* optional: processed positions in order */
     int64_t seq_cap;
+    const uint8_t* dims; /* stored split dimensions, or NULL (by level) */
 } knn_ctx;
 
 static void list_insert(knn_ctx* c, float d2, int32_t idx) {
@@ -160,7 +196,7 @@ static void knn_rec(knn_ctx* c, int64_t pos) {
     if (c->seq && c->visited < c->seq_cap) c->seq[c->visited] = (int32_t)pos;
     c->visited++;
     list_insert(c, d2, pidx);
-    int dim = level_of(pos) % c->D;
+    int dim = c->dims ? c->dims[pos] : level_of(pos) % c->D;
     float sd = c->q[dim] - p[dim];
     int64_t close_c = sd > 0.0f ? 2 * pos + 2 : 2 * pos + 1;
     int64_t far_c = sd > 0.0f ? 2 * pos + 1 : 2 * pos + 2;
@@ -169,15 +205,16 @@ static void knn_rec(knn_ctx* c, int64_t pos) {
     if (sd2 <= c->ld2[c->k - 1]) knn_rec(c, far_c);
 }
 
-/* One kNN query from initial worst squared radius worst0.  Writes k entries.
+/* One kNN query from initial worst squared radius worst0 over a tree with
+ * stored split dimensions dims[N] (NULL: by level).  Writes k entries.
  * Returns the number of non-empty entries (found). */
-int oracle_knn_one(const float* P, const int32_t* order, int64_t N, int D,
-                   const float* q, int k, float worst0, int32_t* out_idx,
-                   float* out_d2, int64_t* visited, int32_t* seq, int64_t seq_cap) {
+int oracle_knn_one_dims(const float* P, const int32_t* order, const uint8_t* dims, int64_t N, int D,
+                        const float* q, int k, float worst0, int32_t* out_idx,
+                        float* out_d2, int64_t* visited, int32_t* seq, int64_t seq_cap) {
     float* ld2 = (float*)malloc((size_t)k * sizeof(float));
     int32_t* lidx = (int32_t*)malloc((size_t)k * sizeof(int32_t));
     for (int j = 0; j < k; ++j) { ld2[j] = worst0; lidx[j] = SENT_IDX; }
-    knn_ctx c = {P, order, N, D, q, k, ld2, lidx, 0, seq, seq_cap};
+    knn_ctx c = {P, order, N, D, q, k, ld2, lidx, 0, seq, seq_cap, dims};
     knn_rec(&c, 0);
     int found = 0;
     for (int j = 0; j < k; ++j) {
@@ -194,6 +231,12 @@ int oracle_knn_one(const float* P, const int32_t* order, int64_t N, int D,
     free(ld2);
     free(lidx);
     return found;
+}
+
+int oracle_knn_one(const float* P, const int32_t* order, int64_t N, int D,
+                   const float* q, int k, float worst0, int32_t* out_idx,
+                   float* out_d2, int64_t* visited, int32_t* seq, int64_t seq_cap) {
+    return oracle_knn_one_dims(P, order, NULL, N, D, q, k, worst0, out_idx, out_d2, visited, seq, seq_cap);
 }
 
 /* worst0 for a predicted radius r0 (learned-radius rule). */
@@ -305,6 +348,7 @@ typedef struct {
     int64_t next;       /* shared chunk cursor */
     pthread_mutex_t mu;
     int64_t* count;     /* radius / box: points found per query */
+    const uint8_t* dims; /* tree mode: stored split dimensions, or NULL */
 } batch_job;
 
 #define CHUNK 4096
@@ -335,7 +379,7 @@ static void* batch_worker(void* arg) {
             float* od = b->out_d2 ? b->out_d2 + i * b->k : NULL;
             int64_t v = 0;
             if (b->mode == 0) {
-                oracle_knn_one(b->P, b->order, b->N, b->D, q, b->k, b->R2, oi, od, &v, NULL, 0);
+                oracle_knn_one_dims(b->P, b->order, b->dims, b->N, b->D, q, b->k, b->R2, oi, od, &v, NULL, 0);
             } else if (b->mode == 1) {
                 oracle_brute_one(b->P, b->N, b->D, q, b->k, b->R2, oi, od);
             } else {
@@ -374,6 +418,16 @@ int oracle_knn_batch(const float* P, const int32_t* order, int64_t N, int D,
                      float* out_d2, int64_t* visited, int nthreads) {
     if (k < 1 || N < 0 || Q < 0) return -1;
     batch_job b = {0, P, order, N, D, queries, Q, k, R2, NULL, out_idx, out_d2, visited, NULL};
+    return run_batch(&b, nthreads);
+}
+
+/* The same over a tree with stored split dimensions dims[N]. */
+int oracle_knn_batch_dims(const float* P, const int32_t* order, const uint8_t* dims, int64_t N, int D,
+                          const float* queries, int64_t Q, int k, float R2, int32_t* out_idx,
+                          float* out_d2, int64_t* visited, int nthreads) {
+    if (k < 1 || N < 0 || Q < 0) return -1;
+    batch_job b = {0, P, order, N, D, queries, Q, k, R2, NULL, out_idx, out_d2, visited, NULL};
+    b.dims = dims;
     return run_batch(&b, nthreads);
 }
 

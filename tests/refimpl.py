@@ -40,7 +40,7 @@ def brute_np(points, q, k, R2):
     return idx, d
 
 
-def ordered_walk(points, order, q, k, R2):
+def ordered_walk(points, order, q, k, R2, dims=None):
     """The ordered traversal of Sec. 3.1 (node first, then the close child,
     then the far child if its split plane is within the current search
     radius) written with an explicit stack of frames, independently of the
@@ -50,7 +50,8 @@ def ordered_walk(points, order, q, k, R2):
     the tour of entered positions -- every node as it is entered and again
     each time a child returns to it --, idx list, d2 list).  The tour is the
     sequence of `curr` values a two-integer state machine passes through: one
-    loop trip per entry."""
+    loop trip per entry.  dims: stored split dimension by position (else the
+    level's, floor(log2(pos + 1)) mod D)."""
     P = np.asarray(points, np.float32)
     N, D = P.shape
     q = np.asarray(q, np.float32)
@@ -67,7 +68,7 @@ def ordered_walk(points, order, q, k, R2):
             stack.pop()
             continue
         p = P[order[pos]]
-        dim = int(np.floor(np.log2(pos + 1))) % D
+        dim = int(dims[pos]) if dims is not None else int(np.floor(np.log2(pos + 1))) % D
         sd = np.float32(q[dim] - p[dim])
         close = 2 * pos + (2 if sd > 0 else 1)
         far = 2 * pos + (1 if sd > 0 else 2)
