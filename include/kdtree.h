@@ -120,8 +120,32 @@ typedef struct {
  *            return all -1.
  *   dim    : 2, 3 or 4.
  *   out    : receives the tree; free with kd_tree_free.
- * Synchronises the stream (the build runs on the host in this version). */
+ * Synchronises the stream (the build runs on the GPU; see kd_build_ex). */
 kd_status kd_build(const float* points, int64_t N, int dim, kd_stream stream, kd_tree* out);
+
+/* Split-dimension rules of kd_build_ex.  The paper leaves the split
+ * dimension to the builder and lets a node carry it (Sec. 3, its assumption
+ * list; Sec. 4, node types with a stored dimension).
+ *   KD_SPLIT_LEVEL  : node at level l splits on l mod dim, nothing stored
+ *                     (the tree of kd_build).
+ *   KD_SPLIT_WIDEST : each node splits on the dimension of largest extent
+ *                     fl32(max - min) of its subtree's points, the lowest
+ *                     dimension on equal extents; the rest of the rule is
+ *                     unchanged (rank leftSize, order by (coordinate in that
+ *                     dimension, caller index)).  Stored as 2 bits per node
+ *                     (one byte per node holding the node's and its three
+ *                     nearest ancestors' dimensions). */
+#define KD_SPLIT_LEVEL 0
+#define KD_SPLIT_WIDEST 1
+
+/* kd_build with a split-dimension rule.  Trees built with KD_SPLIT_WIDEST
+ * are accepted by kd_fcp, kd_knn, kd_knn_ex (opts.lds_levels must be 0),
+ * kd_knn_noalloc, kd_autotune, kd_radius_search and kd_box_search; the
+ * learned-radius calls and batches return KD_EUNSUPPORTED for them.  Results
+ * are the same exact kNN rows for either rule (the set of the k nearest by
+ * (d2, index) does not depend on the tree); processed-node counts differ. */
+kd_status kd_build_ex(const float* points, int64_t N, int dim, int split, kd_stream stream,
+                      kd_tree* out);
 
 /* Same, from a HOST float32 [N][dim] array (no device read of the input). */
 kd_status kd_build_host(const float* host_points, int64_t N, int dim, kd_tree* out);
@@ -140,6 +164,11 @@ kd_status kd_tree_info(kd_tree t, int64_t* N, int* dim, float* bbox_lo4, float* 
 /* Copies the level-order permutation to HOST memory: order[pos] = caller
  * index of the point at tree position pos; order has N entries. */
 kd_status kd_tree_order(kd_tree t, int32_t* host_order);
+
+/* The split dimension of every tree position to HOST memory (uint8 [N];
+ * may be NULL) and the tree's rule (*split = KD_SPLIT_LEVEL or
+ * KD_SPLIT_WIDEST; may be NULL). */
+kd_status kd_tree_dims(kd_tree t, uint8_t* host_dims, int* split);
 
 /* --------------------------------------------------------------- queries */
 

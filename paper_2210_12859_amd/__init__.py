@@ -65,6 +65,8 @@ def lib():
     P, i64, i32, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_float
     sig = {
         "kd_build": ([P, i64, i32, P, P], i32),
+        "kd_build_ex": ([P, i64, i32, i32, P, P], i32),
+        "kd_tree_dims": ([P, P, P], i32),
         "kd_build_host": ([P, i64, i32, P], i32),
         "kd_build_order_host": ([P, i64, i32, P], i32),
         "kd_tree_free": ([P], i32),
@@ -168,6 +170,16 @@ class Tree:
         _check(lib().kd_tree_order(self.handle, out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
+    def dims(self):
+        """(split dimension of every tree position, uint8 [N]; the rule,
+        KD_SPLIT_LEVEL or KD_SPLIT_WIDEST)."""
+        import numpy as np
+        n = self.info()["N"]
+        out = np.empty(n, np.uint8)
+        rule = ctypes.c_int()
+        _check(lib().kd_tree_dims(self.handle, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rule)))
+        return out, rule.value
+
     def close(self):
         if self._h:
             lib().kd_tree_free(self._h)
@@ -180,15 +192,21 @@ class Tree:
             pass
 
 
-def kd_build(points, stream=None) -> Tree:
-    """Canonical left-balanced tree over device float32 points [N][dim]."""
+KD_SPLIT_LEVEL = 0
+KD_SPLIT_WIDEST = 1
+
+
+def kd_build(points, stream=None, split=KD_SPLIT_LEVEL) -> Tree:
+    """Canonical left-balanced tree over device float32 points [N][dim];
+    split: KD_SPLIT_LEVEL (dimension by level) or KD_SPLIT_WIDEST (stored
+    per node, the widest extent of its subtree)."""
     import torch
     _require(points, torch.float32, "points")
     if points.dim() != 2:
         raise ValueError("points must be [N][dim]")
     h = ctypes.c_void_p()
-    _check(lib().kd_build(_ptr(points), points.shape[0], points.shape[1], _stream_handle(stream),
-                          ctypes.byref(h)))
+    _check(lib().kd_build_ex(_ptr(points), points.shape[0], points.shape[1], int(split), _stream_handle(stream),
+                             ctypes.byref(h)))
     return Tree(h.value)
 
 

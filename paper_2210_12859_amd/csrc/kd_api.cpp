@@ -263,6 +263,8 @@ kd_status resolve_plan(kd_tree t, int k, float maxRadius, const kd_opts* o, Quer
     if (use.block != 64 && use.block != 128 && use.block != 256 && use.block != 512 && use.block != 1024)
         return set_error(KD_EINVAL, "opts.block must be 64, 128, 256, 512 or 1024");
     if (use.lds_levels > 12) return set_error(KD_EINVAL, "opts.lds_levels must be <= 12");
+    if (t && t->d_dims && use.lds_levels > 0)
+        return set_error(KD_EINVAL, "opts.lds_levels must be 0 for trees with stored split dimensions");
     if (t && use.lds_levels > 0 && (size_t(1) << use.lds_levels) * 4 * size_t(rec_words(t->dim)) > 65536)
         return set_error(KD_EINVAL, "opts.lds_levels: the staged levels exceed 64 KB of LDS (dim 4: at most 11)");
     if (use.sort_bits > 32) return set_error(KD_EINVAL, "opts.sort_bits must be in 0..32 or -1");
@@ -328,7 +330,13 @@ kd_status kd_build_host(const float* host_points, int64_t N, int dim, kd_tree* o
 }
 
 kd_status kd_build(const float* points, int64_t N, int dim, kd_stream stream, kd_tree* out) {
+    return kd_build_ex(points, N, dim, KD_SPLIT_LEVEL, stream, out);
+}
+
+kd_status kd_build_ex(const float* points, int64_t N, int dim, int split, kd_stream stream, kd_tree* out) {
     if (!out) return set_error(KD_EINVAL, "kd_build: out is NULL");
+    if (split != KD_SPLIT_LEVEL && split != KD_SPLIT_WIDEST)
+        return set_error(KD_EINVAL, "kd_build: split must be KD_SPLIT_LEVEL or KD_SPLIT_WIDEST");
     if (N < 0 || N > KD_MAX_POINTS) return set_error(KD_EINVAL, "kd_build: N out of range [0, 2^30 - 1]");
     if (dim < 2 || dim > 4) return set_error(KD_EINVAL, "kd_build: dim must be 2, 3 or 4");
     if (N > 0 && !points) return set_error(KD_EINVAL, "kd_build: points is NULL");
@@ -341,6 +349,7 @@ kd_status kd_build(const float* points, int64_t N, int dim, kd_stream stream, kd
     if (!t) return set_error(KD_ENOMEM, "kd_build: host allocation");
     t->N = N;
     t->dim = dim;
+    t->split = split;
     KD_HIP(hipGetDevice(&t->device));
     for (int j = 0; j < 4; ++j) t->lo[j] = t->hi[j] = 0.0f;
     if (N == 0) {
@@ -359,15 +368,38 @@ kd_status kd_build(const float* points, int64_t N, int dim, kd_stream stream, kd
         int32_t* p;
         ~FreeOrder() { (void)hipFree(p); }
     } guard{d_order};
-    s = build_level_order_device(points, N, dim, d_order, st);
-    if (s != KD_OK) return s;
-    KD_HIP(hipMalloc(&t->d_nodes, node_buffer_bytes(dim, N)));
-    hipError_t e = hipMalloc(&t->d_boxes, box_buffer_bytes(dim, N));
+    uint8_t* d_pos_dims = nullptr;
+    struct FreeDims {
+        uint8_t** p;
+        ~FreeDims() { (void)hipFree(*p); }
+    } guard_dims{&d_pos_dims};
+    if (split == KD_SPLIT_WIDEST) {
+        try {
+            t->pos_dims.resize(size_t(N));
+        } catch (...) {
+            return set_error(KD_ENOMEM, "kd_build: host allocation");
+        }
+        KD_HIP(hipMalloc(&d_pos_dims, size_t(N)));
+        KD_HIP(hipMalloc(&t->d_dims, size_t(N) + 2));
+    }
+    s = build_level_order_device(points, N, dim, d_order, st, d_pos_dims);
+    if (s != KD_OK) {
+        if (t->d_dims) (void)hipFree(t->d_dims);
+        return s;
+    }
+    hipError_t e = hipMalloc(&t->d_nodes, node_buffer_bytes(dim, N));
+    if (e != hipSuccess) {
+        if (t->d_dims) (void)hipFree(t->d_dims);
+        return hip_error(e, "kd_build: nodes");
+    }
+    e = hipMalloc(&t->d_boxes, box_buffer_bytes(dim, N));
     if (e != hipSuccess) {
         (void)hipFree(t->d_nodes);
+        if (t->d_dims) (void)hipFree(t->d_dims);
         return hip_error(e, "kd_build: boxes");
     }
-    s = pack_tree_device(points, d_order, N, dim, t->d_nodes, static_cast<float*>(t->d_boxes), st);
+    s = pack_tree_device(points, d_order, N, dim, t->d_nodes, static_cast<float*>(t->d_boxes), st, d_pos_dims,
+                         t->d_dims);
     float root_box[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (s == KD_OK) {
         e = hipMemcpyAsync(t->order.data(), d_order, size_t(N) * 4, hipMemcpyDeviceToHost, st);
@@ -375,12 +407,15 @@ kd_status kd_build(const float* points, int64_t N, int dim, kd_stream stream, kd
         if (e == hipSuccess)
             e = hipMemcpyAsync(root_box, static_cast<float*>(t->d_boxes) + box_words(dim), box_words(dim) * 4,
                                hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && d_pos_dims)
+            e = hipMemcpyAsync(t->pos_dims.data(), d_pos_dims, size_t(N), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) s = hip_error(e, "kd_build: read back");
     }
     if (s != KD_OK) {
         (void)hipFree(t->d_nodes);
         (void)hipFree(t->d_boxes);
+        if (t->d_dims) (void)hipFree(t->d_dims);
         return s;
     }
     for (int j = 0; j < dim; ++j) {
@@ -407,6 +442,7 @@ kd_status kd_tree_free(kd_tree t) {
     if (!t) return KD_OK;
     if (t->d_nodes) (void)hipFree(t->d_nodes);
     if (t->d_boxes) (void)hipFree(t->d_boxes);
+    if (t->d_dims) (void)hipFree(t->d_dims);
     delete t;
     return KD_OK;
 }
@@ -431,6 +467,22 @@ kd_status kd_tree_info(kd_tree t, int64_t* N, int* dim, float* lo4, float* hi4) 
     if (dim) *dim = t->dim;
     if (lo4) std::memcpy(lo4, t->lo, sizeof(t->lo));
     if (hi4) std::memcpy(hi4, t->hi, sizeof(t->hi));
+    return KD_OK;
+}
+
+kd_status kd_tree_dims(kd_tree t, uint8_t* host_dims, int* split) {
+    if (!t) return set_error(KD_EINVAL, "kd_tree_dims: tree is NULL");
+    if (split) *split = t->split;
+    if (!host_dims || t->N == 0) return KD_OK;
+    if (t->split == KD_SPLIT_WIDEST) {
+        std::memcpy(host_dims, t->pos_dims.data(), size_t(t->N));
+    } else {
+        for (int64_t pos = 0; pos < t->N; ++pos) {
+            int lvl = 0;
+            while ((int64_t(2) << lvl) <= pos + 1) ++lvl;  // floor(log2(pos + 1))
+            host_dims[pos] = uint8_t(lvl % t->dim);
+        }
+    }
     return KD_OK;
 }
 

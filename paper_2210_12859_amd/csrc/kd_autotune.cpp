@@ -63,7 +63,9 @@ kd_status kd_autotune(kd_tree t, const float* sample_q, int64_t Qs, int k, float
         for (int w : waves)
             for (int sb : sorts)
                 for (int pr : prunes)
-                    for (int l : ldsl) cands.push_back(kd_opts{b, l, sb, w, 0, pr});
+                    for (int l : ldsl)
+                        if (l == 0 || !t->d_dims)  // stored dimensions: nodes from global memory
+                            cands.push_back(kd_opts{b, l, sb, w, 0, pr});
     }
     int32_t* idx = nullptr;
     float* d2 = nullptr;

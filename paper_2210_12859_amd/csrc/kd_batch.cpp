@@ -227,6 +227,8 @@ kd_status kd_batch_create(const kd_job* jobs, int n_jobs, kd_model model, const 
         const kd_job& J = jobs[i];
         const std::string f = "kd_batch_create: job " + std::to_string(i);
         if (!J.tree) return set_error(KD_EINVAL, f + ": tree is NULL");
+        if (J.tree->split != KD_SPLIT_LEVEL)
+            return set_error(KD_EUNSUPPORTED, f + ": trees with stored split dimensions are not batched");
         if (J.Q < 0 || J.Q >= (int64_t(1) << 31)) return set_error(KD_EINVAL, f + ": Q out of range");
         if (J.k < 1 || J.k > KD_MAX_K) return set_error(KD_EINVAL, f + ": k out of range [1, 64]");
         if (std::isnan(J.maxRadius) || J.maxRadius < 0.0f) return set_error(KD_EINVAL, f + ": bad maxRadius");

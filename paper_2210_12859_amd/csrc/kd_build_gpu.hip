@@ -21,6 +21,14 @@
 // (right child) of the next level.  H levels, each a sort of N keys on l + 1
 // bits.  The result equals the host builder's and the oracle's byte for byte.
 //
+// Stored split dimensions (the widest rule): every segment of the level
+// picks its own dimension, so all D lists are sorted by segment each level.
+// In list L_d a segment's points are in coordinate order, so its extent in d
+// is the coordinate of its last point minus that of its first; the largest
+// extent (the lowest d on ties) is the segment's dimension, and its points
+// are ranked in that dimension's list.  Each point is assigned once, by the
+// list of its segment's dimension.  H levels of D sorts.
+//
 // Node records and subtree boxes are then written on the device as well.
 #include <hip/hip_runtime.h>
 
@@ -97,6 +105,71 @@ __global__ void level_assign(const uint32_t* __restrict__ k, const uint32_t* __r
     }
 }
 
+// Split dimension of each node of the level (widest rule): the extent of
+// segment s in d is the coordinate of its last point minus its first's in
+// the segment-sorted list S_d.
+__global__ void segment_dims(const float* __restrict__ pts, int D, const uint32_t* __restrict__ S0,
+                             const uint32_t* __restrict__ S1, const uint32_t* __restrict__ S2,
+                             const uint32_t* __restrict__ S3, uint32_t nseg, int64_t W, int64_t last, int64_t first,
+                             uint8_t* __restrict__ segdim, uint8_t* __restrict__ pos_dims) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    const int64_t sW = int64_t(s) * W;
+    const int64_t start = int64_t(s) * (W - 1) + (last < sW ? last : sW);
+    int64_t extra = last - sW;
+    extra = extra < 0 ? 0 : (extra > W ? W : extra);
+    const int64_t size = (W - 1) + extra;  // >= 1: node first + s exists
+    const uint32_t* S[4] = {S0, S1, S2, S3};
+    int best = 0;
+    float best_ext = -1.0f;
+    for (int d = 0; d < D; ++d) {
+        const float lo = pts[size_t(S[d][start]) * D + d];
+        const float hi = pts[size_t(S[d][start + size - 1]) * D + d];
+        const float ext = hi - lo;
+        if (ext > best_ext) {
+            best_ext = ext;
+            best = d;
+        }
+    }
+    segdim[s] = uint8_t(best);
+    pos_dims[first + s] = uint8_t(best);
+}
+
+// level_assign for the points of list d whose segment splits in d; the new
+// segments go to seg_next (seg is still read by the other lists' launches).
+__global__ void level_assign_widest(const uint32_t* __restrict__ S, int d, const uint8_t* __restrict__ segdim,
+                                    const uint32_t* __restrict__ seg, uint32_t R, int64_t W, int64_t last,
+                                    int64_t first, int32_t* __restrict__ order, uint32_t* __restrict__ seg_next) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= R) return;
+    const uint32_t p = S[j];
+    const int64_t s = seg[p];  // unplaced: the first R entries of the list
+    if (segdim[s] != d) return;
+    const int64_t sW = s * W;
+    const int64_t start = s * (W - 1) + (last < sW ? last : sW);
+    int64_t extra = last - sW;
+    extra = extra < 0 ? 0 : (extra > W ? W : extra);
+    const int64_t size = (W - 1) + extra;
+    const int64_t m = left_size_dev(size);
+    const int64_t o = int64_t(j) - start;
+    if (o == m) {
+        order[first + s] = int32_t(p);
+        seg_next[p] = PLACED;
+    } else {
+        seg_next[p] = uint32_t(o < m ? 2 * s : 2 * s + 1);
+    }
+}
+
+// Per node id: the split dimensions of the node and its three nearest
+// ancestors, 2 bits each (own dimension in bits 0-1).
+__global__ void pack_dims(const uint8_t* __restrict__ pos_dims, uint32_t N, uint8_t* __restrict__ out) {
+    const uint32_t pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= N) return;
+    uint32_t a = pos + 1, b = 0;
+    for (int m = 0; m < 4 && a >= 1; ++m, a >>= 1) b |= uint32_t(pos_dims[a - 1]) << (2 * m);
+    out[pos + 1] = uint8_t(b);
+}
+
 // Any non-finite coordinate sets *bad.
 __global__ void check_finite(const float* __restrict__ pts, size_t n, uint32_t* __restrict__ bad) {
     for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
@@ -107,7 +180,7 @@ __global__ void check_finite(const float* __restrict__ pts, size_t n, uint32_t* 
 // record or in the index array), ancestor splits (parent first).
 template <int D>
 __global__ void pack_records_dev(const float* __restrict__ pts, const int32_t* __restrict__ order, uint32_t N,
-                                 TreeRec<D>* __restrict__ r) {
+                                 const uint8_t* __restrict__ pos_dims, TreeRec<D>* __restrict__ r) {
     const uint32_t pos = blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= N) return;
     constexpr int A0 = D + (rec_has_idx(D) ? 1 : 0);
@@ -124,7 +197,8 @@ __global__ void pack_records_dev(const float* __restrict__ pts, const int32_t* _
     for (int m = 0; m < rec_ancestors(D); ++m) {
         if (a >= 1) {
             const int lvl = 31 - __builtin_clz(a);
-            rec.w[A0 + m] = __float_as_uint(pts[size_t(order[a - 1]) * D + (lvl % D)]);
+            const int d = pos_dims ? int(pos_dims[a - 1]) : lvl % D;
+            rec.w[A0 + m] = __float_as_uint(pts[size_t(order[a - 1]) * D + d]);
         }
         a >>= 1;
     }
@@ -161,8 +235,82 @@ inline dim3 grid_for(uint64_t n) { return dim3(unsigned((n + 255) / 256)); }
 
 }  // namespace
 
-kd_status build_level_order_device(const float* d_pts, int64_t N, int D, int32_t* d_order, hipStream_t st) {
+namespace {
+kd_status build_widest_device(const float* d_pts, int64_t N, int D, int32_t* d_order, uint8_t* d_pos_dims,
+                              hipStream_t st) {
+    const uint32_t n = uint32_t(N);
+    const size_t b4 = (size_t(n) * 4 + 255) & ~size_t(255);
+    const size_t b1 = (size_t(n) + 255) & ~size_t(255);
+    const size_t hist_b = (sort_pairs_scratch_bytes(n) + 255) & ~size_t(255);
+    // seg | seg_next | L_0 .. L_{D-1} | S_0 .. S_{D-1} | k0 v0 k1 v1 | segdim | histograms
+    char* ws = nullptr;
+    KD_HIP(hipMalloc(&ws, b4 * (2 + 2 * size_t(D) + 4) + b1 + hist_b));
+    struct Free {
+        char* p;
+        ~Free() { (void)hipFree(p); }
+    } guard{ws};
+    uint32_t* seg = reinterpret_cast<uint32_t*>(ws);
+    uint32_t* seg_next = reinterpret_cast<uint32_t*>(ws + b4);
+    uint32_t* L[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint32_t* S[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int d = 0; d < D; ++d) {
+        L[d] = reinterpret_cast<uint32_t*>(ws + b4 * (2 + d));
+        S[d] = reinterpret_cast<uint32_t*>(ws + b4 * (2 + D + d));
+    }
+    char* tail = ws + b4 * (2 + 2 * size_t(D));
+    uint32_t* k0 = reinterpret_cast<uint32_t*>(tail);
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(tail + b4);
+    uint32_t* k1 = reinterpret_cast<uint32_t*>(tail + 2 * b4);
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(tail + 3 * b4);
+    uint8_t* segdim = reinterpret_cast<uint8_t*>(tail + 4 * b4);
+    void* hist = tail + 4 * b4 + b1;
+    const dim3 g = grid_for(n), b(256);
+    for (int d = 0; d < D; ++d) {
+        hipLaunchKernelGGL(dim_keys, g, b, 0, st, d_pts, n, D, d, k0, v0);
+        KD_HIP(hipGetLastError());
+        bool second = false;
+        kd_status s = sort_pairs(k0, v0, k1, v1, n, 32, hist, st, &second);
+        if (s != KD_OK) return s;
+        KD_HIP(hipMemcpyAsync(L[d], second ? v1 : v0, size_t(n) * 4, hipMemcpyDeviceToDevice, st));
+    }
+    hipLaunchKernelGGL(fill_u32, g, b, 0, st, seg, n, 0u);
+    KD_HIP(hipGetLastError());
+    int H = 0;
+    while (H < 31 && (int64_t(1) << H) <= N) ++H;
+    const int64_t last = N - ((int64_t(1) << (H - 1)) - 1);
+    for (int l = 0; l < H; ++l) {
+        const int64_t first = (int64_t(1) << l) - 1;
+        const uint32_t R = uint32_t(N - first);
+        const int64_t W = int64_t(1) << (H - 1 - l);
+        for (int d = 0; d < D; ++d) {
+            hipLaunchKernelGGL(level_keys, g, b, 0, st, L[d], seg, n, uint32_t(1) << l, k0, v0);
+            KD_HIP(hipGetLastError());
+            bool second = false;
+            kd_status s = sort_pairs(k0, v0, k1, v1, n, l + 1, hist, st, &second);
+            if (s != KD_OK) return s;
+            KD_HIP(hipMemcpyAsync(S[d], second ? v1 : v0, size_t(R) * 4, hipMemcpyDeviceToDevice, st));
+        }
+        const int64_t nodes = std::min<int64_t>(int64_t(1) << l, N - first);
+        hipLaunchKernelGGL(segment_dims, grid_for(uint64_t(nodes)), b, 0, st, d_pts, D, S[0], S[1], S[2], S[3],
+                           uint32_t(nodes), W, last, first, segdim, d_pos_dims);
+        KD_HIP(hipGetLastError());
+        KD_HIP(hipMemcpyAsync(seg_next, seg, size_t(n) * 4, hipMemcpyDeviceToDevice, st));
+        for (int d = 0; d < D; ++d) {
+            hipLaunchKernelGGL(level_assign_widest, grid_for(R), b, 0, st, S[d], d, segdim, seg, R, W, last, first,
+                               d_order, seg_next);
+            KD_HIP(hipGetLastError());
+        }
+        std::swap(seg, seg_next);
+    }
+    KD_HIP(hipStreamSynchronize(st));  // the workspace is freed on return
+    return KD_OK;
+}
+}  // namespace
+
+kd_status build_level_order_device(const float* d_pts, int64_t N, int D, int32_t* d_order, hipStream_t st,
+                                   uint8_t* d_pos_dims) {
     if (N <= 0) return KD_OK;
+    if (d_pos_dims) return build_widest_device(d_pts, N, D, d_order, d_pos_dims, st);
     const uint32_t n = uint32_t(N);
     const size_t b4 = (size_t(n) * 4 + 255) & ~size_t(255);
     const size_t hist_b = (sort_pairs_scratch_bytes(n) + 255) & ~size_t(255);
@@ -218,18 +366,29 @@ kd_status build_level_order_device(const float* d_pts, int64_t N, int D, int32_t
 }
 
 kd_status pack_tree_device(const float* d_pts, const int32_t* d_order, int64_t N, int D, void* d_nodes,
-                           float* d_boxes, hipStream_t st) {
+                           float* d_boxes, hipStream_t st, const uint8_t* d_pos_dims, uint8_t* d_dims) {
     if (N <= 0) return KD_OK;
     const uint32_t n = uint32_t(N);
     KD_HIP(hipMemsetAsync(d_nodes, 0, node_buffer_bytes(D, N), st));
     KD_HIP(hipMemsetAsync(d_boxes, 0, box_buffer_bytes(D, N), st));
     const dim3 g = grid_for(n), b(256);
     switch (D) {
-        case 2: hipLaunchKernelGGL(pack_records_dev<2>, g, b, 0, st, d_pts, d_order, n, (TreeRec<2>*)d_nodes); break;
-        case 3: hipLaunchKernelGGL(pack_records_dev<3>, g, b, 0, st, d_pts, d_order, n, (TreeRec<3>*)d_nodes); break;
-        default: hipLaunchKernelGGL(pack_records_dev<4>, g, b, 0, st, d_pts, d_order, n, (TreeRec<4>*)d_nodes); break;
+        case 2:
+            hipLaunchKernelGGL(pack_records_dev<2>, g, b, 0, st, d_pts, d_order, n, d_pos_dims, (TreeRec<2>*)d_nodes);
+            break;
+        case 3:
+            hipLaunchKernelGGL(pack_records_dev<3>, g, b, 0, st, d_pts, d_order, n, d_pos_dims, (TreeRec<3>*)d_nodes);
+            break;
+        default:
+            hipLaunchKernelGGL(pack_records_dev<4>, g, b, 0, st, d_pts, d_order, n, d_pos_dims, (TreeRec<4>*)d_nodes);
+            break;
     }
     KD_HIP(hipGetLastError());
+    if (d_dims) {
+        KD_HIP(hipMemsetAsync(d_dims, 0, size_t(N) + 2, st));
+        hipLaunchKernelGGL(pack_dims, g, b, 0, st, d_pos_dims, n, d_dims);
+        KD_HIP(hipGetLastError());
+    }
     int H = 0;
     while (H < 31 && (int64_t(1) << H) <= N) ++H;
     for (int l = H - 1; l >= 0; --l) {

@@ -88,13 +88,18 @@ struct kd_tree_s {
     int64_t N = 0;
     int dim = 0;
     int device = 0;
+    int split = 0;                 // KD_SPLIT_LEVEL or KD_SPLIT_WIDEST
     float lo[4] = {0, 0, 0, 0};
     float hi[4] = {0, 0, 0, 0};
     void* d_nodes = nullptr;       // node buffer: TreeRec<dim>[N + 2], record of node id i at index i
                                    // (+ int32 index[N + 2] when the record holds no index)
     void* d_boxes = nullptr;       // float[N + 2][box_words(dim)]: bounding box of the points of the
                                    // subtree of node id i (lows, then highs) at index i
+    uint8_t* d_dims = nullptr;     // trees with stored split dimensions: uint8[N + 2] by node id, bits
+                                   // 2m..2m+1 = split dimension of the ancestor m levels up (m = 0:
+                                   // the node); NULL: the dimension of node id i is floor(log2 i) mod dim
     std::vector<int32_t> order;    // host copy: order[pos] = caller index
+    std::vector<uint8_t> pos_dims; // host copy of the stored dimensions by position (else empty)
     std::mutex tune_mu;
     std::vector<kd::TuneEntry> tuned;
 };
@@ -221,10 +226,17 @@ kd_status sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uin
                      hipStream_t st, bool* in_second);
 // Canonical tree on the device (kd_build_gpu.hip): d_order[pos] = caller
 // index of the point at level-order position pos, for device points [N][dim].
-kd_status build_level_order_device(const float* d_pts, int64_t N, int dim, int32_t* d_order, hipStream_t st);
-// Node records and subtree boxes from device points and order (kd_build_gpu.hip).
+// d_pos_dims non-NULL: the widest-extent rule, each position's split
+// dimension written there (uint8 [N]); NULL: the dimension by level.
+kd_status build_level_order_device(const float* d_pts, int64_t N, int dim, int32_t* d_order, hipStream_t st,
+                                   uint8_t* d_pos_dims = nullptr);
+// Node records and subtree boxes from device points and order (kd_build_gpu.hip);
+// with stored dimensions (d_pos_dims by position) the records' ancestor splits
+// follow them and d_dims (uint8 [N + 2], by node id) receives the packed
+// dimensions of each node and its three nearest ancestors.
 kd_status pack_tree_device(const float* d_pts, const int32_t* d_order, int64_t N, int dim, void* d_nodes,
-                           float* d_boxes, hipStream_t st);
+                           float* d_boxes, hipStream_t st, const uint8_t* d_pos_dims = nullptr,
+                           uint8_t* d_dims = nullptr);
 // *ok = no NaN or infinity among the N * dim device floats (synchronises).
 kd_status check_points_finite(const float* d_pts, int64_t N, int dim, hipStream_t st, bool* ok);
 // device scratch of one kd_knn-family call (kd_traverse.hip)

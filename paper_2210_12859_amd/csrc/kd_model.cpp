@@ -101,6 +101,8 @@ kd_status kd_radius_model_train(kd_tree t, const float* train_q, int64_t Qt, int
     if (!out) return set_error(KD_EINVAL, "kd_radius_model_train: out is NULL");
     if (!t) return set_error(KD_EINVAL, "kd_radius_model_train: tree is NULL");
     if (t->dim != 3) return set_error(KD_EUNSUPPORTED, "kd_radius_model_train: the radius model is 3-D");
+    if (t->split != KD_SPLIT_LEVEL)
+        return set_error(KD_EUNSUPPORTED, "kd_radius_model_train: trees with stored split dimensions");
     if (k < 1 || k > KD_MAX_K) return set_error(KD_EINVAL, "kd_radius_model_train: k out of range [1, 64]");
     if (t->N < k) return set_error(KD_EINVAL, "kd_radius_model_train: tree has fewer than k points");
     if (Qt < 128 || Qt >= (int64_t(1) << 31)) return set_error(KD_EINVAL, "kd_radius_model_train: need 128 <= Qt < 2^31");
@@ -311,6 +313,8 @@ kd_status kd_knn_learned(kd_tree t, kd_model m, const float* queries, int64_t Q,
     if (s != KD_OK) return s;
     if (!m) return set_error(KD_EINVAL, "kd_knn_learned: model is NULL");
     if (t->dim != 3) return set_error(KD_EUNSUPPORTED, "kd_knn_learned: the radius model is 3-D");
+    if (t->split != KD_SPLIT_LEVEL)
+        return set_error(KD_EUNSUPPORTED, "kd_knn_learned: trees with stored split dimensions");
     if (stats) *stats = kd_stats{0, 0, 0, 0, 0.0f, 0.0f, 0.0f, 0.0f};
     if (Q == 0 || t->N == 0)
         return knn_entry(t, queries, Q, k, maxRadius, out_idx, out_d2, visited, opts, stream, "kd_knn_learned");
@@ -331,6 +335,8 @@ kd_status kd_knn_with_radius(kd_tree t, const float* r0, const float* queries, i
     kd_status s = check_query_args_public(t, queries, Q, k, maxRadius, out_idx, "kd_knn_with_radius");
     if (s != KD_OK) return s;
     if (Q > 0 && !r0) return set_error(KD_EINVAL, "kd_knn_with_radius: r0 is NULL");
+    if (t->split != KD_SPLIT_LEVEL)
+        return set_error(KD_EUNSUPPORTED, "kd_knn_with_radius: trees with stored split dimensions");
     if (Q == 0 || t->N == 0) {
         s = knn_entry(t, queries, Q, k, maxRadius, out_idx, out_d2, visited, opts, stream, "kd_knn_with_radius");
         if (s == KD_OK && fell_back && Q > 0)

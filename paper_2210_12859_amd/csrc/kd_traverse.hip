@@ -61,6 +61,7 @@ constexpr uint32_t SENT_IDX = 0x7fffffffu;
 
 struct TravArgs {
     const void* nodes;       // TreeRec<D>[N + 2], record of node id i at index i
+    const uint8_t* dims;     // stored split dimensions by node id (XD kernels), else NULL
     const float* boxes;      // [N + 2][box_words(D)] subtree bounding boxes (BOX kernels)
     int32_t box_below;       // boxes are tested for node ids below this (subtrees tall enough)
     int32_t lds_below;       // LDS kernels: records of node ids 1 .. lds_below-1 are staged in LDS
@@ -154,6 +155,15 @@ constexpr uint32_t dim_pattern(int D, int j) {
 template <int D>
 struct DimSel {
     bool f[4];  // f[j]: dim == j (f[0] unused)
+    DimSel() = default;
+    // a stored dimension d (0 .. D-1)
+    static __device__ __forceinline__ DimSel of(uint32_t d) {
+        DimSel r;
+        r.f[0] = false;
+#pragma unroll
+        for (int j = 1; j < 4; ++j) r.f[j] = j < D && d == uint32_t(j);
+        return r;
+    }
     __device__ __forceinline__ explicit DimSel(int32_t id) {
         const uint32_t c = uint32_t(__builtin_clz(uint32_t(id)));  // id >= 1
         f[0] = false;
@@ -180,6 +190,16 @@ struct DimSel {
         return rot<I>(v[0], v[1], D > 2 ? v[D > 2 ? 2 : 0] : 0.0f, D > 3 ? v[D > 3 ? 3 : 0] : 0.0f);
     }
 };
+
+// Split dimension of node `id` at `up` levels above it (0: the node): by
+// level, or (XD, trees with stored dimensions) from the node's dimension
+// byte db, which holds 2 bits for the node and each of its three nearest
+// ancestors.  rot<0> of the result picks that node's split coordinate.
+template <int D, bool XD, int UP>
+__device__ __forceinline__ DimSel<D> split_dim(int32_t id, uint32_t db) {
+    if constexpr (XD) return DimSel<D>::of((db >> (2 * UP)) & 3u);
+    else return DimSel<D>(id >> UP);
+}
 
 // Whole-record loads: one or two dwordx4 from one aligned record.
 template <int D>
@@ -390,14 +410,14 @@ __device__ __forceinline__ void lane_finish(const Lane<D, K>& s, const TravArgs&
 // is the caller-index array when records hold no index): the state-machine
 // step at curr, then up to F fused "return to parent" steps.  Returns the new
 // curr (0 = traversal finished).
-template <int D, int K, int F, bool CAP = false, bool FAR = true>
+template <int D, int K, int F, bool CAP = false, bool FAR = true, bool XD = false>
 __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D], int32_t idx,
                                              const int32_t* __restrict__ ids,
                                              const float (&anc)[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1],
                                              int32_t N, float cap = 0.0f, int32_t stop = 0,
-                                             bool skip = false) {
+                                             bool skip = false, uint32_t db = 0) {
     const int32_t curr = s.curr;
-    const DimSel<D> dim(curr);
+    const DimSel<D> dim = split_dim<D, XD, 0>(curr, db);
     float dx[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) dx[j] = s.q[j] - c[j];
@@ -455,7 +475,10 @@ __device__ __forceinline__ int32_t lane_step(Lane<D, K>& s, const float (&c)[D],
         const bool live = up & (anc_id != stop);  // stop: parent of the traversal's root
         {
             if (live) {
-                const float sda = dim.template rot<i + 1>(s.q) - anc[i];
+                float qa;
+                if constexpr (XD) qa = split_dim<D, true, i + 1>(curr, db).template rot<0>(s.q);
+                else qa = dim.template rot<i + 1>(s.q);
+                const float sda = qa - anc[i];
                 const bool child_is_close = (child & 1) == (sda > 0.0f ? 1 : 0);
                 const int32_t fa = child ^ 1;
                 const bool take_far = child_is_close & (sda * sda <= worst) & (fa <= N);
@@ -626,7 +649,7 @@ constexpr int min_waves(int K) { return K >= 64 ? KD_MIN_WAVES_K64 : 1; }
 // nodes read them from there.  The traversal itself is unchanged.
 extern __shared__ uint4 kd_lds_nodes[];
 
-template <int D, int K, int F, bool LEARNED, bool BOX, bool LDSN>
+template <int D, int K, int F, bool LEARNED, bool BOX, bool LDSN, bool XD = false>
 __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(TravArgs a) {
     const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);  // indexed by node id
     const int32_t* __restrict__ ids = node_ids<D>(g1, a.N);
@@ -707,6 +730,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
             if (LDSN && s.curr < a.lds_below) load_tree<D>(lrec + s.curr, c, idx, anc);
             else load_tree<D>(g1 + s.curr, c, idx, anc);
+            const uint32_t db = XD ? uint32_t(a.dims[s.curr]) : 0u;
             bool skip = false;
             if constexpr (BOX) {
                 // entering a far subtree of height >= KD_BOX_MIN_HEIGHT:
@@ -715,7 +739,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
                     skip = box_d2<D>(a.boxes, s.curr, s.q) > key_d2(s.L[K - 1]);
             }
             const int32_t stop = LEARNED ? s.stop : 0;
-            const int32_t next = lane_step<D, K, F, false, BOX>(s, c, idx, ids, anc, a.N, 0.0f, stop, skip);
+            const int32_t next = lane_step<D, K, F, false, BOX, XD>(s, c, idx, ids, anc, a.N, 0.0f, stop, skip, db);
             const bool done = next == stop;
             bool handed = false;
             // every running lane steps once per wave trip, so a query's trip
@@ -785,6 +809,7 @@ __global__ __launch_bounds__(max_block(K), min_waves(K)) void knn_persistent(Tra
 #endif
 struct CoopArgs {
     const void* nodes;
+    const uint8_t* dims;     // stored split dimensions by node id (XD kernel), else NULL
     const float* boxes;      // subtree bounding boxes, or NULL (split planes only)
     int32_t box_below;       // boxes are tested for node ids below this
     int32_t N;
@@ -855,7 +880,7 @@ __device__ __forceinline__ float coop_bound(const uint64_t (&L)[K], int k) {
     return __uint_as_float(a < b ? a : b);
 }
 
-template <int D, int K>
+template <int D, int K, bool XD = false>
 __global__ __launch_bounds__(256) void knn_coop(CoopArgs a) {
     const uint32_t lane = __lane_id();
     const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -949,7 +974,7 @@ __global__ __launch_bounds__(256) void knn_coop(CoopArgs a) {
                         if (key < s.L[K - 1]) list_insert<K>(s.L, key);
                     }
                 }
-                const DimSel<D> dim(tcurr);
+                const DimSel<D> dim = split_dim<D, XD, 0>(tcurr, XD ? uint32_t(a.dims[tcurr]) : 0u);
                 const float sd = dim.template rot<0>(dx);
                 const int32_t close_c = (tcurr << 1) | (sd > 0.0f ? 1 : 0);
                 const int32_t far_c = close_c ^ 1;
@@ -968,9 +993,10 @@ __global__ __launch_bounds__(256) void knn_coop(CoopArgs a) {
                 int32_t idx;
                 float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
                 load_tree<D>(g1 + s.curr, c, idx, anc);
+                const uint32_t db = XD ? uint32_t(a.dims[s.curr]) : 0u;
                 const bool skip = boxes != nullptr && s.far_entry && s.curr < box_below &&
                                   box_d2<D>(boxes, s.curr, s.q) > fminf(key_d2(s.L[K - 1]), bound);
-                lane_step<D, K, fused_levels(D), true>(s, c, idx, ids, anc, N, bound, stop, skip);
+                lane_step<D, K, fused_levels(D), true, true, XD>(s, c, idx, ids, anc, N, bound, stop, skip, db);
                 if (s.curr == stop) s.curr = 0;
             }
             // the wave-wide bound is refreshed every 8 trips (a stale bound
@@ -1015,6 +1041,13 @@ hipError_t launch_knn(const TravArgs& a, bool learned, int block, int grid, size
     const bool box = a.boxes != nullptr;
     constexpr int F = fused_levels(D);
     const dim3 g(grid), b(block);
+    if (a.dims) {
+        // stored split dimensions: plain queries, nodes from global memory
+        if (learned || lds_bytes) return hipErrorInvalidValue;
+        if (box) hipLaunchKernelGGL((knn_persistent<D, K, F, false, true, false, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((knn_persistent<D, K, F, false, false, false, true>), g, b, 0, st, a);
+        return hipGetLastError();
+    }
     if (learned && box) hipLaunchKernelGGL((knn_persistent<D, K, F, true, true, false>), g, b, 0, st, a);
     else if (learned) hipLaunchKernelGGL((knn_persistent<D, K, F, true, false, false>), g, b, 0, st, a);
     else if (lds_bytes && box) hipLaunchKernelGGL((knn_persistent<D, K, F, false, true, true>), g, b, lds_bytes, st, a);
@@ -1075,6 +1108,20 @@ hipError_t dispatch_dk(int D, int K, const TravArgs& a, bool learned, int block,
 template <int D>
 hipError_t launch_coop_k(int K, const CoopArgs& a, int grid, hipStream_t st) {
     const dim3 g(grid), b(256);
+    if (a.dims) {
+        if (a.jobs) return hipErrorInvalidValue;  // batches hold level-rule trees only
+        switch (K) {
+            case 1: hipLaunchKernelGGL((knn_coop<D, 1, true>), g, b, 0, st, a); break;
+            case 2: hipLaunchKernelGGL((knn_coop<D, 2, true>), g, b, 0, st, a); break;
+            case 4: hipLaunchKernelGGL((knn_coop<D, 4, true>), g, b, 0, st, a); break;
+            case 8: hipLaunchKernelGGL((knn_coop<D, 8, true>), g, b, 0, st, a); break;
+            case 16: hipLaunchKernelGGL((knn_coop<D, 16, true>), g, b, 0, st, a); break;
+            case 32: hipLaunchKernelGGL((knn_coop<D, 32, true>), g, b, 0, st, a); break;
+            case 64: hipLaunchKernelGGL((knn_coop<D, 64, true>), g, b, 0, st, a); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (K) {
         case 1: hipLaunchKernelGGL((knn_coop<D, 1>), g, b, 0, st, a); break;
         case 2: hipLaunchKernelGGL((knn_coop<D, 2>), g, b, 0, st, a); break;
@@ -1558,6 +1605,9 @@ struct StageEvents {
 kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan, int32_t* out_idx,
                   float* out_d2, uint32_t* visited, kd_stream stream, const LearnedSpec* learned,
                   kd_stats* stats, const FixedScratch* fixed) {
+    if (t->d_dims && (learned || plan.lds_levels > 0))
+        return set_error(KD_EUNSUPPORTED, "trees with stored split dimensions take plain queries with nodes read "
+                                          "from global memory (no learned radius, opts.lds_levels 0)");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const DeviceInfo& dev = device_info(t->device);
     void* ws = nullptr;
@@ -1648,6 +1698,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
 
     TravArgs a = {};
     a.nodes = t->d_nodes;
+    a.dims = t->d_dims;
     a.boxes = use_boxes ? static_cast<const float*>(t->d_boxes) : nullptr;
     a.box_below = box_id_limit(t->N);
     a.refill_min = (use_boxes || plan.K == 1) ? 4u : 1u;  // measured best, see KD_REFILL_MIN_BATCHED
@@ -1713,6 +1764,7 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
         // the device; waves beyond it exit at once)
         CoopArgs c = {};
         c.nodes = t->d_nodes;
+        c.dims = t->d_dims;
         c.boxes = a.boxes;
         c.box_below = a.box_below;
         c.N = int32_t(t->N);
@@ -1770,6 +1822,7 @@ namespace {
 
 struct RangeArgs {
     const void* nodes;      // TreeRec<D>[N + 2]
+    const uint8_t* dims;    // stored split dimensions by node id (XD kernels), else NULL
     int32_t N;
     const void* recs;       // NodeRec<D>[Q] Morton-sorted: the query point (radius) or the box centre
     const float* boxes;     // box queries: caller float [Q][2][D]
@@ -1814,15 +1867,15 @@ __device__ __forceinline__ void range_finish(const RangeLane<D, K, BOXQ>& s, con
 // Which children the query region reaches, at a node of split dimension sel
 // with split value sv.
 template <int D, int K, bool BOXQ>
-__device__ __forceinline__ void range_wants(const RangeLane<D, K, BOXQ>& s, const DimSel<D>& sel, int rot, float sv,
+__device__ __forceinline__ void range_wants(const RangeLane<D, K, BOXQ>& s, const DimSel<D>& sel, float sv,
                                             float R2, bool& want_l, bool& want_r) {
     if constexpr (BOXQ) {
-        const float lo = rot == 0 ? sel.template rot<0>(s.a) : sel.template rot<1>(s.a);
-        const float hi = rot == 0 ? sel.template rot<0>(s.b) : sel.template rot<1>(s.b);
+        const float lo = sel.template rot<0>(s.a);
+        const float hi = sel.template rot<0>(s.b);
         want_l = lo <= sv;
         want_r = hi >= sv;
     } else {
-        const float qd = rot == 0 ? sel.template rot<0>(s.a) : sel.template rot<1>(s.a);
+        const float qd = sel.template rot<0>(s.a);
         const float sd = qd - sv;
         const bool far = sd * sd > R2;
         want_l = !(sd > 0.0f && far);
@@ -1830,7 +1883,7 @@ __device__ __forceinline__ void range_wants(const RangeLane<D, K, BOXQ>& s, cons
     }
 }
 
-template <int D, int K, bool BOXQ>
+template <int D, int K, bool BOXQ, bool XD>
 __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
     const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);
     const int32_t* __restrict__ ids = node_ids<D>(g1, a.N);
@@ -1914,6 +1967,7 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
             int32_t idx;
             float anc[rec_ancestors(D) > 0 ? rec_ancestors(D) : 1];
             load_tree<D>(g1 + curr, c, idx, anc);
+            const uint32_t db = XD ? uint32_t(a.dims[curr]) : 0u;
             const bool from_parent = s.prev < curr;
             if (from_parent) {
                 ++s.vis;
@@ -1942,9 +1996,9 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
                     if (key < s.L[K - 1]) list_insert<K>(s.L, key);
                 }
             }
-            const DimSel<D> sel(curr);
+            const DimSel<D> sel = split_dim<D, XD, 0>(curr, db);
             bool want_l, want_r;
-            range_wants<D, K, BOXQ>(s, sel, 0, sel.template rot<0>(c), a.R2, want_l, want_r);
+            range_wants<D, K, BOXQ>(s, sel, sel.template rot<0>(c), a.R2, want_l, want_r);
             const int32_t lc = curr << 1, rc = lc | 1;
             int32_t next, nprev = curr;
             if (from_parent && want_l && lc <= a.N) next = lc;
@@ -1956,7 +2010,7 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
                 next = p;
                 if (p != 0 && (curr & 1) == 0) {
                     bool pl, pr;
-                    range_wants<D, K, BOXQ>(s, sel, 1, anc[0], a.R2, pl, pr);
+                    range_wants<D, K, BOXQ>(s, split_dim<D, XD, 1>(curr, db), anc[0], a.R2, pl, pr);
                     if (pr && (curr | 1) <= a.N) {
                         next = curr | 1;
                         nprev = p;
@@ -1989,8 +2043,14 @@ __global__ void box_centres(const float* __restrict__ boxes, int64_t Q, int D, f
 
 template <int D, int K>
 hipError_t launch_range_k(const RangeArgs& a, bool box, int grid, hipStream_t st) {
-    if (box) hipLaunchKernelGGL((range_persistent<D, K, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((range_persistent<D, K, false>), dim3(grid), dim3(256), 0, st, a);
+    const dim3 g(grid), b(256);
+    if (a.dims) {
+        if (box) hipLaunchKernelGGL((range_persistent<D, K, true, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((range_persistent<D, K, false, true>), g, b, 0, st, a);
+    } else {
+        if (box) hipLaunchKernelGGL((range_persistent<D, K, true, false>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((range_persistent<D, K, false, false>), g, b, 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -2049,6 +2109,7 @@ kd_status run_range(kd_tree t, const float* queries_or_boxes, int64_t Q, bool bo
     if (s != KD_OK) return s;
     a.recs = sq;
     a.nodes = t->d_nodes;
+    a.dims = t->d_dims;
     a.N = int32_t(t->N);
     a.Q = uint32_t(Q);
     a.R2 = R2;
