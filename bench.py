@@ -441,6 +441,74 @@ def range_queries(args):
           flush=True)
 
 
+def split_rules(args):
+    """Trees whose split dimension is the level's against trees that store
+    each node's widest extent, on the same points and queries: build time
+    (untimed elsewhere), processed nodes per query under the paper's rule,
+    and the traversal time of one call under the paper's rule and under the
+    library default (subtree boxes).  Both trees give the same exact rows,
+    which is checked on every query."""
+    import numpy as np
+    import torch
+
+    import paper_2210_12859_amd as kd
+    from paper_2210_12859_amd import datagen
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    cells = []
+    for wl, k in (("uniform-1m", 8), ("gmm64-1m", 8), ("clustered-10m", 16), ("shells-100m", 32)):
+        maxr = DEFAULT_RADIUS.get(wl, math.inf)
+        P, Qs = datagen.workload(wl)
+        p = torch.from_numpy(P).to(dev)
+        q = torch.from_numpy(Qs).to(dev)
+        del P, Qs
+        Q = q.shape[0]
+        res = {}
+        for name, split in (("level", kd.KD_SPLIT_LEVEL), ("widest", kd.KD_SPLIT_WIDEST)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tree = kd.kd_build(p, split=split)
+            build_s = time.perf_counter() - t0
+            oi = torch.empty((Q, k), dtype=torch.int32, device=dev)
+            od = torch.empty((Q, k), dtype=torch.float32, device=dev)
+            vis = torch.empty(Q, dtype=torch.int32, device=dev)
+            kd.kd_knn_ex(tree, q, k, maxr, out_idx=oi, out_d2=od, visited=vis)
+            torch.cuda.synchronize()
+            cell = {"build_s": build_s, "visited_per_query": float(vis.to(torch.float64).mean().item())}
+            del vis
+            for rule, opts in (("paper_rule", PLAIN), ("default", None)):
+                kd.kd_knn_ex(tree, q, k, maxr, out_idx=oi, out_d2=od, opts=opts)
+                reps = 3 if Q <= 10_000_000 else 1
+                kd.kd_timing_enable(True)
+                kd.kd_timing_collect("traverse")
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    kd.kd_knn_ex(tree, q, k, maxr, out_idx=oi, out_d2=od, opts=opts)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                kt, kn = kd.kd_timing_collect("traverse")
+                kd.kd_timing_enable(False)
+                cell[rule + "_ms"] = e0.elapsed_time(e1) / reps
+                cell[rule + "_traverse_ms"] = kt / max(1, kn)
+            res[name] = (cell, oi, od)
+            tree.close()
+        li, ld = res["level"][1], res["level"][2]
+        wi, wd = res["widest"][1], res["widest"][2]
+        same = bool(torch.equal(li, wi) and torch.equal(ld.view(torch.int32), wd.view(torch.int32)))
+        row = {"workload": wl, "k": k, "maxRadius": maxr, "identical_rows": same,
+               "level": res["level"][0], "widest": res["widest"][0]}
+        lv, wv = row["level"], row["widest"]
+        log(f"{wl} k={k}: visited {lv['visited_per_query']:.1f} -> {wv['visited_per_query']:.1f}, paper rule "
+            f"{lv['paper_rule_ms']:.2f} -> {wv['paper_rule_ms']:.2f} ms, default {lv['default_ms']:.2f} -> "
+            f"{wv['default_ms']:.2f} ms, build {lv['build_s']:.3f} -> {wv['build_s']:.3f} s, identical {same}")
+        cells.append(row)
+        del res, li, ld, wi, wd, p, q
+        torch.cuda.empty_cache()
+    print(json.dumps({"split_rules": cells}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,11 +528,16 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--paper-grid", action="store_true",
                     help="only run the shape of the paper's Table 1 (4-D, N 1K..200M, 10M queries)")
+    ap.add_argument("--split-rules", action="store_true",
+                    help="only compare level-rule trees with stored widest-extent dimensions")
     ap.add_argument("--range", action="store_true",
                     help="only run the radius and box search measurement (1M-point 3-D workloads)")
     args = ap.parse_args()
     if args.range:
         range_queries(args)
+        return
+    if args.split_rules:
+        split_rules(args)
         return
     if args.copy_calibration:
         copy_calibration()
