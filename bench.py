@@ -360,11 +360,13 @@ def paper_grid(args):
 
 def range_queries(args):
     """Radius and box search (the un-ordered traversal) on the 1M-point 3-D
-    workloads: regions sized for a mean of 8 and 64 points, results kept for
-    the 8 nearest / smallest indices or counts only.  Per cell: queries/s of
-    one call (Morton reorder + traversal), the traversal kernel's average
-    duration from the library's events on the call's stream, entered nodes
-    per query, the HBM roofline fraction of the entered nodes' coordinates,
+    workloads: regions sized for a mean of 8 and 64 points on uniform data,
+    results kept for the 8 nearest / smallest indices or counts only.  Per
+    cell and pruning mode (split planes only, the paper's traversal and the
+    default; subtree bounding boxes on request): queries/s of one call (Morton
+    reorder + traversal), the traversal kernel's average duration from the
+    library's events on the call's stream, entered nodes per query; for split
+    planes also the HBM roofline fraction of the entered nodes' coordinates;
     and exactness of 256 sampled rows against the oracle's definitions."""
     import numpy as np
     import torch
@@ -387,53 +389,58 @@ def range_queries(args):
         for kind, m, cap in (("radius", 8, 8), ("radius", 64, 0), ("box", 8, 8), ("box", 64, 0)):
             if kind == "radius":
                 size = (3.0 * m / (4.0 * math.pi * N)) ** (1.0 / 3.0)
-                call = lambda v=None: kd.kd_radius_search(tree, q, size, cap, visited=v)
+                oc, oi, od = oracle.radius(P, Qs[rows], size, cap)
             else:
                 size = 0.5 * (m / N) ** (1.0 / 3.0)  # half-width of a cube holding m points on average
                 lo_np = Qs - np.float32(size)
                 hi_np = Qs + np.float32(size)
                 lo = torch.from_numpy(lo_np).to(dev)
                 hi = torch.from_numpy(hi_np).to(dev)
-                call = lambda v=None: kd.kd_box_search(tree, lo, hi, cap, visited=v)
-            res = call(vis)
-            torch.cuda.synchronize()
-            entered = int(vis.to(torch.int64).sum().item())
-            cnt = res[0][r_t].cpu().numpy().astype(np.int64)
-            idx = res[1][r_t].cpu().numpy() if cap else None
-            if kind == "radius":
-                oc, oi, od = oracle.radius(P, Qs[rows], size, cap)
-                ok = bool(np.array_equal(cnt, oc) and (not cap or (
-                    np.array_equal(idx, oi) and np.array_equal(res[2][r_t].cpu().numpy().view(np.uint32),
-                                                               od.view(np.uint32)))))
-            else:
                 oc, oi = oracle.box(P, lo_np[rows], hi_np[rows], cap)
-                ok = bool(np.array_equal(cnt, oc) and (not cap or np.array_equal(idx, oi)))
-            mean_count = float(res[0].to(torch.float64).mean().item())
-            for _ in range(args.warmup):
-                call()
-            torch.cuda.synchronize()
-            kd.kd_timing_enable(True)
-            kd.kd_timing_collect(kind)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(args.steps):
-                call()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / args.steps
-            kt, kn = kd.kd_timing_collect(kind)
-            kd.kd_timing_enable(False)
-            kern_ms = kt / max(1, kn)
-            alg = entered * D * 4
-            gbs = alg / (kern_ms / 1e3) / 1e9
-            cell = {"workload": wl, "kind": kind, "size": size, "cap": cap, "mean_count": mean_count,
-                    "qps": Q / (ms / 1e3), "ms_per_call": ms, "kernel_ms": kern_ms,
-                    "entered_per_query": entered / Q, "alg_bytes_per_launch": alg,
-                    "roofline_frac": gbs / HBM_PEAK_GBPS, "exact_on_sample": ok}
-            log(f"{wl} {kind} size={size:.4g} cap={cap}: {cell['qps'] / 1e6:.1f} M q/s, kernel {kern_ms:.3f} ms, "
-                f"{mean_count:.1f} in range, entered {entered / Q:.1f}/query, frac {cell['roofline_frac']:.3f}, "
-                f"exact {ok}")
+            cell = {"workload": wl, "kind": kind, "size": size, "cap": cap}
+            for mode, flags in (("planes", 0), ("boxes", kd.KD_RANGE_BOXES)):
+                if kind == "radius":
+                    call = lambda v=None, f=flags: kd.kd_radius_search(tree, q, size, cap, visited=v, flags=f)
+                else:
+                    call = lambda v=None, f=flags: kd.kd_box_search(tree, lo, hi, cap, visited=v, flags=f)
+                res = call(vis)
+                torch.cuda.synchronize()
+                entered = int(vis.to(torch.int64).sum().item())
+                cnt = res[0][r_t].cpu().numpy().astype(np.int64)
+                ok = bool(np.array_equal(cnt, oc))
+                if cap:
+                    ok = ok and bool(np.array_equal(res[1][r_t].cpu().numpy(), oi))
+                    if kind == "radius":
+                        ok = ok and bool(np.array_equal(res[2][r_t].cpu().numpy().view(np.uint32), od.view(np.uint32)))
+                cell["mean_count"] = float(res[0].to(torch.float64).mean().item())
+                for _ in range(args.warmup):
+                    call()
+                torch.cuda.synchronize()
+                kd.kd_timing_enable(True)
+                kd.kd_timing_collect(kind)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(args.steps):
+                    call()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                kt, kn = kd.kd_timing_collect(kind)
+                kd.kd_timing_enable(False)
+                kern_ms = kt / max(1, kn)
+                cell[mode] = {"qps": Q / (ms / 1e3), "ms_per_call": ms, "kernel_ms": kern_ms,
+                              "entered_per_query": entered / Q, "exact_on_sample": ok}
+                if mode == "planes":
+                    alg = entered * D * 4
+                    cell[mode]["alg_bytes_per_launch"] = alg
+                    cell[mode]["roofline_frac"] = alg / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBPS
+            pl, df = cell["planes"], cell["boxes"]
+            log(f"{wl} {kind} size={size:.4g} cap={cap}: {cell['mean_count']:.1f} in range; planes "
+                f"{pl['qps'] / 1e6:.1f} M q/s, kernel {pl['kernel_ms']:.3f} ms, entered {pl['entered_per_query']:.1f}, "
+                f"frac {pl['roofline_frac']:.3f}; boxes {df['qps'] / 1e6:.1f} M q/s, kernel {df['kernel_ms']:.3f} ms, "
+                f"entered {df['entered_per_query']:.1f} ({pl['kernel_ms'] / df['kernel_ms']:.2f}x); "
+                f"exact {pl['exact_on_sample'] and df['exact_on_sample']}")
             cells.append(cell)
         tree.close()
     print(json.dumps({"range_queries": cells, "steps": args.steps, "warmup": args.warmup,

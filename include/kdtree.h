@@ -247,14 +247,27 @@ kd_status kd_knn_noalloc(kd_tree t, const float* queries, int64_t Q, int k, floa
  *               the last.
  *   out_d2    : device float32 [Q][cap] or NULL; +inf after the last.
  *   visited   : device uint32 [Q] or NULL: nodes the traversal entered
- *               (first visits, each processed once).
+ *               (first visits; a subtree left at its root by the box test
+ *               counts its root only).
+ *   flags     : 0: split planes only, the paper's un-ordered traversal
+ *               (every point in range is processed).  KD_RANGE_BOXES: a
+ *               subtree is also tested against its bounding box when
+ *               entered: left at once when the box and the query region are
+ *               disjoint and, with cap = 0, counted whole (without visiting
+ *               it) when the box lies inside the region.  Both tests are
+ *               exact in binary32 (counts and rows do not depend on the
+ *               flag).  The box tests pay for count-only queries over
+ *               regions holding thousands of points (clustered 1M points,
+ *               ~10^4 per region: 1.8-2.0x); on small regions, and whenever
+ *               rows are kept, they cost more than they save.
  * An empty tree gives counts 0.  A NaN query has no point in range.
  * Scratch: the per-stream workspace of the kd_knn family (query records and
  * sort buffers, kd_workspace_size(Q)); queries are taken in Morton order.
  * Asynchronous on `stream`. */
+#define KD_RANGE_BOXES 1
 kd_status kd_radius_search(kd_tree t, const float* queries, int64_t Q, float maxRadius, int cap,
                            int32_t* out_idx, float* out_d2, uint32_t* out_count, uint32_t* visited,
-                           kd_stream stream);
+                           int flags, kd_stream stream);
 
 /* All points inside axis-aligned boxes (the un-ordered traversal of Sec. 3,
  * each child entered only when the box reaches its side of the split plane).
@@ -265,11 +278,11 @@ kd_status kd_radius_search(kd_tree t, const float* queries, int64_t Q, float max
  *   cap       : 0..KD_MAX_K;  out_idx : device int32 [Q][cap]: the cap
  *               smallest caller indices inside, ascending, -1 after the last.
  *   out_count : device uint32 [Q]: the number of points inside.
- *   visited   : device uint32 [Q] or NULL, as kd_radius_search.
+ *   visited, flags : as kd_radius_search.
  * Boxes are taken in the Morton order of their centres (the per-stream
  * workspace holds the centres too).  Asynchronous on `stream`. */
 kd_status kd_box_search(kd_tree t, const float* boxes, int64_t Q, int cap, int32_t* out_idx,
-                        uint32_t* out_count, uint32_t* visited, kd_stream stream);
+                        uint32_t* out_count, uint32_t* visited, int flags, kd_stream stream);
 
 /* ------------------------------------------------- learned initial radius */
 

@@ -76,8 +76,8 @@ def lib():
         "kd_knn": ([P, P, i64, i32, f32, P, P, P], i32),
         "kd_knn_ex": ([P, P, i64, i32, f32, P, P, P, P, P], i32),
         "kd_knn_noalloc": ([P, P, i64, i32, f32, P, P, P], i32),
-        "kd_radius_search": ([P, P, i64, f32, i32, P, P, P, P, P], i32),
-        "kd_box_search": ([P, P, i64, i32, P, P, P, P], i32),
+        "kd_radius_search": ([P, P, i64, f32, i32, P, P, P, P, i32, P], i32),
+        "kd_box_search": ([P, P, i64, i32, P, P, P, i32, P], i32),
         "kd_radius_model_train": ([P, P, i64, i32, P, P, P], i32),
         "kd_knn_learned": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
         "kd_knn_with_radius": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
@@ -287,11 +287,15 @@ def kd_knn_noalloc(tree: Tree, queries, k, max_radius=math.inf, out_idx=None, ou
     return out_idx, out_d2
 
 
-def kd_radius_search(tree: Tree, queries, max_radius, cap=0, want_d2=True, visited=None, stream=None):
+KD_RANGE_BOXES = 1
+
+
+def kd_radius_search(tree: Tree, queries, max_radius, cap=0, want_d2=True, visited=None, flags=0, stream=None):
     """Points within max_radius of each query: (count [Q], idx int32 [Q][cap],
     d2 float32 [Q][cap]); idx/d2 are None when cap is 0.  Counts come back
     in an int32 tensor (the library writes uint32; counts stay below 2^30).
-    visited: optional int32 [Q] tensor receiving the entered-node counts."""
+    visited: optional int32 [Q] tensor receiving the entered-node counts.
+    flags: 0 (split planes only) or KD_RANGE_BOXES (also subtree boxes)."""
     import torch
     _require(queries, torch.float32, "queries")
     Q = queries.shape[0]
@@ -304,11 +308,11 @@ def kd_radius_search(tree: Tree, queries, max_radius, cap=0, want_d2=True, visit
     if visited is not None:
         _require(visited, torch.int32, "visited", (Q,))
     _check(lib().kd_radius_search(tree.handle, _ptr(queries), Q, float(max_radius), int(cap), _ptr(idx),
-                                  _ptr(d2), _ptr(count), _ptr(visited), _stream_handle(stream)))
+                                  _ptr(d2), _ptr(count), _ptr(visited), int(flags), _stream_handle(stream)))
     return count, idx, d2
 
 
-def kd_box_search(tree: Tree, lo, hi, cap=0, visited=None, stream=None):
+def kd_box_search(tree: Tree, lo, hi, cap=0, visited=None, flags=0, stream=None):
     """Points inside the boxes [lo, hi] (inclusive): (count [Q], idx int32
     [Q][cap] or None when cap is 0); visited as kd_radius_search."""
     import torch
@@ -323,7 +327,7 @@ def kd_box_search(tree: Tree, lo, hi, cap=0, visited=None, stream=None):
     if visited is not None:
         _require(visited, torch.int32, "visited", (Q,))
     _check(lib().kd_box_search(tree.handle, _ptr(boxes), Q, int(cap), _ptr(idx), _ptr(count), _ptr(visited),
-                               _stream_handle(stream)))
+                               int(flags), _stream_handle(stream)))
     return count, idx
 
 

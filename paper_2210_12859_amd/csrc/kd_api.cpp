@@ -510,8 +510,10 @@ kd_status kd_knn_ex(kd_tree t, const float* queries, int64_t Q, int k, float max
 
 namespace {
 kd_status range_entry(kd_tree t, const float* in, int64_t Q, bool box, float maxRadius, int cap, int32_t* out_idx,
-                      float* out_d2, uint32_t* out_count, uint32_t* visited, kd_stream stream, const char* fn) {
+                      float* out_d2, uint32_t* out_count, uint32_t* visited, int flags, kd_stream stream,
+                      const char* fn) {
     std::string f(fn);
+    if (flags & ~KD_RANGE_BOXES) return set_error(KD_EINVAL, f + ": unknown flags");
     if (Q < 0 || Q >= (int64_t(1) << 31)) return set_error(KD_EINVAL, f + ": Q out of range [0, 2^31)");
     if (cap < 0 || cap > KD_MAX_K) return set_error(KD_EINVAL, f + ": cap out of range [0, 64]");
     if (!box && (std::isnan(maxRadius) || maxRadius < 0.0f))
@@ -539,19 +541,19 @@ kd_status range_entry(kd_tree t, const float* in, int64_t Q, bool box, float max
     }
     const float R2 = box ? 0.0f : maxRadius * maxRadius;  // binary32 product; +inf stays +inf
     return run_range(t, in, Q, box, R2, cap, cap > 0 ? out_idx : nullptr, box || cap == 0 ? nullptr : out_d2,
-                     out_count, visited, stream);
+                     out_count, visited, (flags & KD_RANGE_BOXES) == 0, stream);
 }
 }  // namespace
 
 kd_status kd_radius_search(kd_tree t, const float* queries, int64_t Q, float maxRadius, int cap, int32_t* out_idx,
-                           float* out_d2, uint32_t* out_count, uint32_t* visited, kd_stream stream) {
-    return range_entry(t, queries, Q, false, maxRadius, cap, out_idx, out_d2, out_count, visited, stream,
+                           float* out_d2, uint32_t* out_count, uint32_t* visited, int flags, kd_stream stream) {
+    return range_entry(t, queries, Q, false, maxRadius, cap, out_idx, out_d2, out_count, visited, flags, stream,
                        "kd_radius_search");
 }
 
 kd_status kd_box_search(kd_tree t, const float* boxes, int64_t Q, int cap, int32_t* out_idx, uint32_t* out_count,
-                        uint32_t* visited, kd_stream stream) {
-    return range_entry(t, boxes, Q, true, 0.0f, cap, out_idx, nullptr, out_count, visited, stream,
+                        uint32_t* visited, int flags, kd_stream stream) {
+    return range_entry(t, boxes, Q, true, 0.0f, cap, out_idx, nullptr, out_count, visited, flags, stream,
                        "kd_box_search");
 }
 

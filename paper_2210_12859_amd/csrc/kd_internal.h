@@ -257,9 +257,11 @@ struct FixedScratch {
 // float [Q][dim] points and R2 the squared radius; box = true, it holds float
 // [Q][2][dim] boxes.  Writes out_count[Q] and, for cap > 0, out_idx[Q][cap]
 // (and out_d2[Q][cap] for radius queries when given), and visited[Q] (the
-// entered nodes) when given.  Q >= 1, N >= 1.
+// entered nodes) when given.  Q >= 1, N >= 1.  planes_only: no subtree box
+// tests (split planes only).
 kd_status run_range(kd_tree t, const float* queries_or_boxes, int64_t Q, bool box, float R2, int cap,
-                    int32_t* out_idx, float* out_d2, uint32_t* out_count, uint32_t* visited, kd_stream stream);
+                    int32_t* out_idx, float* out_d2, uint32_t* out_count, uint32_t* visited, bool planes_only,
+                    kd_stream stream);
 kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan, int32_t* out_idx,
                   float* out_d2, uint32_t* visited, kd_stream stream, const LearnedSpec* learned = nullptr,
                   kd_stats* stats = nullptr, const FixedScratch* fixed = nullptr);

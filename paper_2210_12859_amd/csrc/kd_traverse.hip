@@ -1818,11 +1818,36 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
 // box queries.  One "return to parent" level is fused as in the kNN step: a
 // lane leaving a left child decides its parent's right child from the split
 // stored in the child's record.
+//
+// With subtree bounding boxes (on request), a subtree is also tested when it
+// is entered from its parent: it is left at once when its box and the query
+// region are disjoint, and, for count-only queries (cap = 0), counted whole
+// and left when its box lies inside the region.  Both tests are exact in
+// binary32: rounding is monotone, so for every point p of a box and every
+// dimension |fl(q - p)| lies between the offsets to the box's nearer and
+// farther faces, and the left-to-right sum of squares of non-negative terms
+// is monotone in each term; a point's d2 is therefore at least the box's
+// smallest and at most its largest such sum.
 namespace {
+
+// Points in the subtree of node id `id` (a complete tree of N nodes in level
+// order): the full width of every level below it, cut at N.
+__device__ __forceinline__ uint32_t subtree_size(int32_t id, int32_t N) {
+    uint32_t n = 0;
+    int64_t lo = id, hi = id;
+    while (lo <= N) {
+        n += uint32_t((hi < N ? hi : N) - lo + 1);
+        lo <<= 1;
+        hi = (hi << 1) | 1;
+    }
+    return n;
+}
 
 struct RangeArgs {
     const void* nodes;      // TreeRec<D>[N + 2]
     const uint8_t* dims;    // stored split dimensions by node id (XD kernels), else NULL
+    const float* sboxes;    // subtree bounding boxes [N + 2][box_words(D)] (SB kernels)
+    int32_t box_below;      // boxes are tested for node ids below this
     int32_t N;
     const void* recs;       // NodeRec<D>[Q] Morton-sorted: the query point (radius) or the box centre
     const float* boxes;     // box queries: caller float [Q][2][D]
@@ -1883,7 +1908,51 @@ __device__ __forceinline__ void range_wants(const RangeLane<D, K, BOXQ>& s, cons
     }
 }
 
-template <int D, int K, bool BOXQ, bool XD>
+// The subtree of node `id` against the query region: disjoint (no point can
+// be in range), or (count-only queries) wholly inside it.
+template <int D, int K, bool BOXQ>
+__device__ __forceinline__ void range_box_test(const RangeLane<D, K, BOXQ>& s, const float* __restrict__ boxes,
+                                               int32_t id, float R2, bool want_inside, bool& disjoint,
+                                               bool& inside) {
+    constexpr int H = box_words(D) / 2;
+    const uint4* p = reinterpret_cast<const uint4*>(boxes + int64_t(id) * box_words(D));
+    float w[8];
+    const uint4 u = p[0];
+    w[0] = __uint_as_float(u.x); w[1] = __uint_as_float(u.y); w[2] = __uint_as_float(u.z); w[3] = __uint_as_float(u.w);
+    if (box_words(D) == 8) {
+        const uint4 v = p[1];
+        w[4] = __uint_as_float(v.x); w[5] = __uint_as_float(v.y); w[6] = __uint_as_float(v.z); w[7] = __uint_as_float(v.w);
+    }
+    if constexpr (BOXQ) {
+        bool out = false, in = true;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            out = out | (w[H + j] < s.a[j]) | (w[j] > s.b[j]);
+            in = in & (s.a[j] <= w[j]) & (w[H + j] <= s.b[j]);
+        }
+        disjoint = out;
+        inside = want_inside & in;
+    } else {
+        float near[D], far[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const float below = s.a[j] - w[j];      // >= 0 when q is above the low face
+            const float above = s.a[j] - w[H + j];  // <= 0 when q is below the high face
+            near[j] = below < 0.0f ? below : (above > 0.0f ? above : 0.0f);
+            far[j] = fmaxf(fabsf(below), fabsf(above));
+        }
+        float dmin = near[0] * near[0], dmax = far[0] * far[0];
+#pragma unroll
+        for (int j = 1; j < D; ++j) {
+            dmin = dmin + near[j] * near[j];
+            dmax = dmax + far[j] * far[j];
+        }
+        disjoint = dmin > R2;
+        inside = want_inside & (dmax <= R2);
+    }
+}
+
+template <int D, int K, bool BOXQ, bool XD, bool SB>
 __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
     const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);
     const int32_t* __restrict__ ids = node_ids<D>(g1, a.N);
@@ -1969,7 +2038,17 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
             load_tree<D>(g1 + curr, c, idx, anc);
             const uint32_t db = XD ? uint32_t(a.dims[curr]) : 0u;
             const bool from_parent = s.prev < curr;
-            if (from_parent) {
+            bool skip = false;
+            if constexpr (SB) {
+                if (from_parent && curr < a.box_below) {
+                    bool disjoint, inside;
+                    range_box_test<D, K, BOXQ>(s, a.sboxes, curr, a.R2, a.cap == 0, disjoint, inside);
+                    if (inside) s.count += subtree_size(curr, a.N);
+                    skip = disjoint | inside;
+                }
+            }
+            if (from_parent & skip) ++s.vis;  // entered, and left at once
+            if (from_parent & !skip) {
                 ++s.vis;
                 bool in;
                 uint64_t key;
@@ -2001,8 +2080,8 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
             range_wants<D, K, BOXQ>(s, sel, sel.template rot<0>(c), a.R2, want_l, want_r);
             const int32_t lc = curr << 1, rc = lc | 1;
             int32_t next, nprev = curr;
-            if (from_parent && want_l && lc <= a.N) next = lc;
-            else if ((from_parent || s.prev == lc) && want_r && rc <= a.N) next = rc;
+            if (from_parent && !skip && want_l && lc <= a.N) next = lc;
+            else if (((from_parent && !skip) || s.prev == lc) && want_r && rc <= a.N) next = rc;
             else {
                 // return to the parent p; from a left child, p's right child
                 // is decided here from p's split (stored in this record)
@@ -2041,16 +2120,22 @@ __global__ void box_centres(const float* __restrict__ boxes, int64_t Q, int D, f
     out[i] = boxes[q * 2 * D + j] * 0.5f + boxes[q * 2 * D + D + j] * 0.5f;
 }
 
+template <int D, int K, bool XD>
+void launch_range_kx(const RangeArgs& a, bool box, int grid, hipStream_t st) {
+    const dim3 g(grid), b(256);
+    if (a.sboxes) {
+        if (box) hipLaunchKernelGGL((range_persistent<D, K, true, XD, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((range_persistent<D, K, false, XD, true>), g, b, 0, st, a);
+    } else {
+        if (box) hipLaunchKernelGGL((range_persistent<D, K, true, XD, false>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((range_persistent<D, K, false, XD, false>), g, b, 0, st, a);
+    }
+}
+
 template <int D, int K>
 hipError_t launch_range_k(const RangeArgs& a, bool box, int grid, hipStream_t st) {
-    const dim3 g(grid), b(256);
-    if (a.dims) {
-        if (box) hipLaunchKernelGGL((range_persistent<D, K, true, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((range_persistent<D, K, false, true>), g, b, 0, st, a);
-    } else {
-        if (box) hipLaunchKernelGGL((range_persistent<D, K, true, false>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((range_persistent<D, K, false, false>), g, b, 0, st, a);
-    }
+    if (a.dims) launch_range_kx<D, K, true>(a, box, grid, st);
+    else launch_range_kx<D, K, false>(a, box, grid, st);
     return hipGetLastError();
 }
 
@@ -2071,7 +2156,8 @@ hipError_t launch_range(int K, const RangeArgs& a, bool box, int grid, hipStream
 }  // namespace
 
 kd_status run_range(kd_tree t, const float* queries_or_boxes, int64_t Q, bool box, float R2, int cap,
-                    int32_t* out_idx, float* out_d2, uint32_t* out_count, uint32_t* visited, kd_stream stream) {
+                    int32_t* out_idx, float* out_d2, uint32_t* out_count, uint32_t* visited, bool planes_only,
+                    kd_stream stream) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const DeviceInfo& dev = device_info(t->device);
     const int sort_bits = 16;
@@ -2110,6 +2196,8 @@ kd_status run_range(kd_tree t, const float* queries_or_boxes, int64_t Q, bool bo
     a.recs = sq;
     a.nodes = t->d_nodes;
     a.dims = t->d_dims;
+    a.sboxes = planes_only ? nullptr : static_cast<const float*>(t->d_boxes);
+    a.box_below = box_id_limit(t->N);
     a.N = int32_t(t->N);
     a.Q = uint32_t(Q);
     a.R2 = R2;

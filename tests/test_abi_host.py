@@ -71,21 +71,21 @@ def test_range_validation():
     L = kd.lib()
     cnt = P(8)
     # radius: cap, Q, radius, tree, NULL outputs
-    assert L.kd_radius_search(None, P(8), 4, 1.0, 65, P(8), None, cnt, None, None) == kd.KD_EINVAL
+    assert L.kd_radius_search(None, P(8), 4, 1.0, 65, P(8), None, cnt, None, 0, None) == kd.KD_EINVAL
     assert "cap out of range" in L.kd_last_error().decode()
-    assert L.kd_radius_search(None, P(8), 4, 1.0, -1, P(8), None, cnt, None, None) == kd.KD_EINVAL
-    assert L.kd_radius_search(None, P(8), -1, 1.0, 1, P(8), None, cnt, None, None) == kd.KD_EINVAL
+    assert L.kd_radius_search(None, P(8), 4, 1.0, -1, P(8), None, cnt, None, 0, None) == kd.KD_EINVAL
+    assert L.kd_radius_search(None, P(8), -1, 1.0, 1, P(8), None, cnt, None, 0, None) == kd.KD_EINVAL
     assert "Q out of range" in L.kd_last_error().decode()
-    assert L.kd_radius_search(None, P(8), 4, -1.0, 1, P(8), None, cnt, None, None) == kd.KD_EINVAL
+    assert L.kd_radius_search(None, P(8), 4, -1.0, 1, P(8), None, cnt, None, 0, None) == kd.KD_EINVAL
     assert "maxRadius" in L.kd_last_error().decode()
-    assert L.kd_radius_search(None, P(8), 4, float("nan"), 1, P(8), None, cnt, None, None) == kd.KD_EINVAL
-    assert L.kd_radius_search(None, P(8), 4, 1.0, 1, P(8), None, cnt, None, None) == kd.KD_EINVAL
+    assert L.kd_radius_search(None, P(8), 4, float("nan"), 1, P(8), None, cnt, None, 0, None) == kd.KD_EINVAL
+    assert L.kd_radius_search(None, P(8), 4, 1.0, 1, P(8), None, cnt, None, 0, None) == kd.KD_EINVAL
     assert "tree is NULL" in L.kd_last_error().decode()
     # box: cap, Q, tree
-    assert L.kd_box_search(None, P(8), 4, 65, P(8), cnt, None, None) == kd.KD_EINVAL
+    assert L.kd_box_search(None, P(8), 4, 65, P(8), cnt, None, 0, None) == kd.KD_EINVAL
     assert "cap out of range" in L.kd_last_error().decode()
-    assert L.kd_box_search(None, P(8), 1 << 31, 1, P(8), cnt, None, None) == kd.KD_EINVAL
-    assert L.kd_box_search(None, P(8), 4, 0, None, cnt, None, None) == kd.KD_EINVAL
+    assert L.kd_box_search(None, P(8), 1 << 31, 1, P(8), cnt, None, 0, None) == kd.KD_EINVAL
+    assert L.kd_box_search(None, P(8), 4, 0, None, cnt, None, 0, None) == kd.KD_EINVAL
     assert "tree is NULL" in L.kd_last_error().decode()
 
 

@@ -5,7 +5,10 @@ The traversal is the un-ordered form of the stack-free loop (Sec. 3): it
 must process every point inside the query region exactly once, so the bar is
 exact: counts equal, indices byte-identical and squared distances
 bit-identical, row by row.  Radius rows are also kd_knn's rows for
-k = cap within the same radius."""
+k = cap within the same radius.  Both pruning modes are covered: split planes
+only (the paper's traversal, the default) and subtree bounding boxes on
+request (disjoint subtrees skipped, subtrees inside the region counted whole
+when only counts are asked for)."""
 import math
 
 import numpy as np
@@ -32,8 +35,11 @@ def _build(P):
     return kd.kd_build(_t(P))
 
 
-def _radius(tree, Qs, maxr, cap):
-    c, i, d = kd.kd_radius_search(tree, _t(Qs), maxr, cap)
+BOXES = kd.KD_RANGE_BOXES
+
+
+def _radius(tree, Qs, maxr, cap, flags=0):
+    c, i, d = kd.kd_radius_search(tree, _t(Qs), maxr, cap, flags=flags)
     torch.cuda.synchronize()
     Q = Qs.shape[0]
     return (c.cpu().numpy().astype(np.int64),
@@ -41,8 +47,8 @@ def _radius(tree, Qs, maxr, cap):
             None if d is None else d.cpu().numpy().reshape(Q, cap))
 
 
-def _box(tree, lo, hi, cap):
-    c, i = kd.kd_box_search(tree, _t(lo), _t(hi), cap)
+def _box(tree, lo, hi, cap, flags=0):
+    c, i = kd.kd_box_search(tree, _t(lo), _t(hi), cap, flags=flags)
     torch.cuda.synchronize()
     return c.cpu().numpy().astype(np.int64), None if i is None else i.cpu().numpy().reshape(lo.shape[0], cap)
 
@@ -86,7 +92,8 @@ def test_radius_uniform(oracle_lib, D):
     for cap in (0, 1, 7, 64):
         print(f"[gpu] radius uniform D={D} cap={cap}", flush=True)
         want = oracle_lib.radius(P, Qs, maxr, cap)
-        _same_radius(_radius(tree, Qs, maxr, cap), want, cap, f"D={D} cap={cap}")
+        for flags in (0, BOXES):
+            _same_radius(_radius(tree, Qs, maxr, cap, flags), want, cap, f"D={D} cap={cap} flags={flags}")
     # rows equal kd_knn's within the same radius
     gi, gd = kd.kd_knn(tree, _t(Qs), 8, maxr)
     _, ri, rd = _radius(tree, Qs, maxr, 8)
@@ -105,7 +112,8 @@ def test_box_uniform(oracle_lib, D):
     for cap in (0, 1, 5, 64):
         print(f"[gpu] box uniform D={D} cap={cap}", flush=True)
         want = oracle_lib.box(P, lo, hi, cap)
-        _same_box(_box(tree, lo, hi, cap), want, cap, f"D={D} cap={cap}")
+        for flags in (0, BOXES):
+            _same_box(_box(tree, lo, hi, cap, flags), want, cap, f"D={D} cap={cap} flags={flags}")
     tree.close()
 
 
@@ -121,7 +129,8 @@ def test_radius_ties_on_grid(oracle_lib):
         for cap in (0, 16, 64):
             print(f"[gpu] radius grid maxr={maxr} cap={cap}", flush=True)
             want = oracle_lib.radius(P, Qs, maxr, cap)
-            _same_radius(_radius(tree, Qs, maxr, cap), want, cap, f"grid maxr={maxr} cap={cap}")
+            for flags in (0, BOXES):
+                _same_radius(_radius(tree, Qs, maxr, cap, flags), want, cap, f"grid maxr={maxr} cap={cap} f={flags}")
     tree.close()
 
 
@@ -142,7 +151,8 @@ def test_box_ties_degenerate_and_invalid(oracle_lib):
     for cap in (0, 3, 64):
         print(f"[gpu] box grid cap={cap}", flush=True)
         want = oracle_lib.box(P, lo, hi, cap)
-        _same_box(_box(tree, lo, hi, cap), want, cap, f"grid boxes cap={cap}")
+        for flags in (0, BOXES):
+            _same_box(_box(tree, lo, hi, cap, flags), want, cap, f"grid boxes cap={cap} flags={flags}")
     c, _ = _box(tree, lo[500:1200], hi[500:1200], 0)
     assert not c.any()
     tree.close()
@@ -158,18 +168,21 @@ def test_radius_infinite_nan_and_small_trees(oracle_lib):
         tree = _build(P)
         for maxr, cap in ((math.inf, 64), (math.inf, 0), (0.3, 5), (0.0, 1)):
             want = oracle_lib.radius(P, Qs, maxr, cap)
-            got = _radius(tree, Qs, maxr, cap)
-            _same_radius(got, want, cap, f"N={N} maxr={maxr} cap={cap}")
-            if maxr == math.inf:
-                assert (got[0][np.isfinite(Qs).all(axis=1)] == N).all()
-                assert got[0][7] == 0 and got[0][8] == 0
+            for flags in (0, BOXES):
+                got = _radius(tree, Qs, maxr, cap, flags)
+                _same_radius(got, want, cap, f"N={N} maxr={maxr} cap={cap} flags={flags}")
+                if maxr == math.inf:
+                    assert (got[0][np.isfinite(Qs).all(axis=1)] == N).all()
+                    assert got[0][7] == 0 and got[0][8] == 0
         tree.close()
 
 
 def test_visited_counts_and_unbounded_regions(oracle_lib):
-    """Entered-node counts: every point in the region is entered, nothing is
-    entered twice, and an unbounded region (infinite radius, infinite box
-    faces) enters all N nodes."""
+    """Entered-node counts under split planes only (the default): every point
+    in the region is entered, nothing is entered twice, and an unbounded
+    region (infinite radius, infinite box faces) enters all N nodes.  With
+    subtree boxes and counts only, the unbounded region is counted at the
+    root."""
     rng = np.random.default_rng(8)
     N, Q = 20_000, 4_000
     P = rng.random((N, 3), dtype=np.float32)
@@ -195,6 +208,42 @@ def test_visited_counts_and_unbounded_regions(oracle_lib):
     assert (c[:100] == N).all() and (v[:100] == N).all()
     oc, _ = oracle_lib.box(P, lo, hi, 0)
     assert np.array_equal(c, oc)
+    # subtree boxes, counts only: the whole tree is counted at the root
+    c, _ = kd.kd_box_search(tree, _t(lo), _t(hi), 0, visited=vis, flags=BOXES)
+    cr, _, _ = kd.kd_radius_search(tree, q, math.inf, 0, flags=BOXES)
+    torch.cuda.synchronize()
+    assert np.array_equal(c.cpu().numpy(), oc) and (vis.cpu().numpy()[:100] == 1).all()
+    assert (cr.cpu().numpy() == N).all()
+    tree.close()
+
+
+def test_whole_subtree_counts_on_large_regions(oracle_lib):
+    """Count-only queries over regions holding thousands of clustered points:
+    with subtree boxes, subtrees inside the region are counted without being
+    visited, the counts still equal the definition's, and far fewer nodes are
+    entered than with split planes alone."""
+    P, Qs = datagen.workload("gmm64-1m")
+    rows = np.random.default_rng(12).choice(Qs.shape[0], 3000, replace=False)
+    Qs = Qs[rows]
+    tree = _build(P)
+    q = _t(Qs)
+    v0 = torch.empty(len(Qs), dtype=torch.int32, device=_dev())
+    v1 = torch.empty(len(Qs), dtype=torch.int32, device=_dev())
+    for maxr in (0.01, 0.03):
+        print(f"[gpu] range gmm64 count-only radius {maxr}", flush=True)
+        c0, _, _ = kd.kd_radius_search(tree, q, maxr, 0, visited=v0, flags=BOXES)
+        c1, _, _ = kd.kd_radius_search(tree, q, maxr, 0, visited=v1)
+        torch.cuda.synchronize()
+        oc, _, _ = oracle_lib.radius(P, Qs, maxr, 0)
+        assert np.array_equal(c0.cpu().numpy(), oc) and np.array_equal(c1.cpu().numpy(), oc)
+        assert v0.sum().item() * 2 < v1.sum().item()
+        h = np.float32(maxr)
+        b0, _ = kd.kd_box_search(tree, _t(Qs - h), _t(Qs + h), 0, visited=v0, flags=BOXES)
+        b1, _ = kd.kd_box_search(tree, _t(Qs - h), _t(Qs + h), 0, visited=v1)
+        torch.cuda.synchronize()
+        ob, _ = oracle_lib.box(P, Qs - h, Qs + h, 0)
+        assert np.array_equal(b0.cpu().numpy(), ob) and np.array_equal(b1.cpu().numpy(), ob)
+        assert v0.sum().item() * 2 < v1.sum().item()
     tree.close()
 
 

@@ -134,6 +134,13 @@ def test_range_queries(oracle_lib):
     assert np.array_equal(d.cpu().numpy().view(np.uint32), od.view(np.uint32))
     oc, oi = oracle_lib.box(P, Qs - h, Qs + h, 16)
     assert np.array_equal(bc.cpu().numpy(), oc) and np.array_equal(bi.cpu().numpy(), oi)
+    # counts only, with and without subtree boxes
+    orc, _, _ = oracle_lib.radius(P, Qs, 0.5, 0)
+    for flags in (0, kd.KD_RANGE_BOXES):
+        c, _, _ = kd.kd_radius_search(tree, _t(Qs), 0.5, 0, flags=flags)
+        bc, _ = kd.kd_box_search(tree, _t(Qs - h), _t(Qs + h), 0, flags=flags)
+        torch.cuda.synchronize()
+        assert np.array_equal(c.cpu().numpy(), orc) and np.array_equal(bc.cpu().numpy(), oc)
     tree.close()
 
 
