@@ -16,6 +16,12 @@ bounding box is out of range ("boxes", identical results, fewer nodes), the
 learned-radius variant on the same queries ("learned", paper's rule), a
 batched many-tree measurement ("batched") and the CPU oracle timed on the
 host ("cpu_baseline"); each can be skipped by a flag.
+
+Other measurements, each printing its own JSON line instead of the headline:
+  --paper-grid   the shape of the paper's Table 1 (4-D, N 1K..200M, 10M queries)
+  --range        radius and box search on the 1M-point 3-D workloads
+  --split-rules  level-rule trees against stored widest-extent dimensions
+  --copy-calibration  a plain 1 GiB copy, the reference for HBM counters
 """
 from __future__ import annotations
 
@@ -435,11 +441,23 @@ def range_queries(args):
                     alg = entered * D * 4
                     cell[mode]["alg_bytes_per_launch"] = alg
                     cell[mode]["roofline_frac"] = alg / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBPS
+            # the oracle (the plain definition, brute force over all N points,
+            # one thread per host core) on a bounded sample of the same queries
+            ns = 2048
+            t0 = time.perf_counter()
+            if kind == "radius":
+                oracle.radius(P, Qs[:ns], size, cap)
+            else:
+                oracle.box(P, lo_np[:ns], hi_np[:ns], cap)
+            cell["cpu_baseline"] = {"value": ns / (time.perf_counter() - t0), "unit": "queries/s",
+                                    "cores": oracle.default_threads(), "kind": "oracle",
+                                    "sample": f"first {ns} queries, brute force over all {N} points"}
             pl, df = cell["planes"], cell["boxes"]
             log(f"{wl} {kind} size={size:.4g} cap={cap}: {cell['mean_count']:.1f} in range; planes "
                 f"{pl['qps'] / 1e6:.1f} M q/s, kernel {pl['kernel_ms']:.3f} ms, entered {pl['entered_per_query']:.1f}, "
                 f"frac {pl['roofline_frac']:.3f}; boxes {df['qps'] / 1e6:.1f} M q/s, kernel {df['kernel_ms']:.3f} ms, "
                 f"entered {df['entered_per_query']:.1f} ({pl['kernel_ms'] / df['kernel_ms']:.2f}x); "
+                f"oracle {cell['cpu_baseline']['value'] / 1e3:.1f} K q/s; "
                 f"exact {pl['exact_on_sample'] and df['exact_on_sample']}")
             cells.append(cell)
         tree.close()
@@ -501,6 +519,20 @@ def split_rules(args):
                 cell[rule + "_traverse_ms"] = kt / max(1, kn)
             res[name] = (cell, oi, od)
             tree.close()
+        if wl != "shells-100m":
+            # the oracle over the widest tree (recursive traversal with stored
+            # dimensions, one thread per host core) on a bounded sample
+            import oracle
+            Pn = p.cpu().numpy()
+            qn = q[: 1 << 16].cpu().numpy()
+            order, dims = oracle.build_tree_widest(Pn)  # untimed
+            t0 = time.perf_counter()
+            oracle.knn(Pn, order, qn, k, maxr, dims=dims)
+            res["widest"][0]["cpu_baseline"] = {
+                "value": qn.shape[0] / (time.perf_counter() - t0), "unit": "queries/s",
+                "cores": oracle.default_threads(), "kind": "oracle",
+                "sample": f"first {qn.shape[0]} queries, recursive traversal over the widest tree"}
+            del Pn, qn, order, dims
         li, ld = res["level"][1], res["level"][2]
         wi, wd = res["widest"][1], res["widest"][2]
         same = bool(torch.equal(li, wi) and torch.equal(ld.view(torch.int32), wd.view(torch.int32)))
