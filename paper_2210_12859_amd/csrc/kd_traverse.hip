@@ -1861,83 +1861,63 @@ struct RangeArgs {
     uint32_t* counter;      // chunk cursor, zero at launch
 };
 
-template <int D, int K, bool BOXQ>
-struct RangeLane {
-    float a[D];        // radius: the query point; box: low corner
-    float b[BOXQ ? D : 1];  // box: high corner
-    uint64_t L[K];
-    int32_t curr, prev, row;
-    uint32_t count, vis;
-};
-
-template <int D, int K, bool BOXQ>
-__device__ __forceinline__ void range_finish(const RangeLane<D, K, BOXQ>& s, const RangeArgs& a) {
-    a.out_count[s.row] = s.count;
-    if (a.visited) a.visited[s.row] = s.vis;
-    if (a.cap == 0) return;
-    int32_t* oi = a.out_idx + int64_t(s.row) * a.cap;
-    float* od = (!BOXQ && a.out_d2) ? a.out_d2 + int64_t(s.row) * a.cap : nullptr;
-    const int off = K - a.cap;
+// The two query kinds as compile-time policies of one kernel: the paper's
+// processNode and its "is this subtree in range" test passed as template
+// parameters (Sec. 4 makes processNode a template parameter of the kernel).
+// A policy holds a query's region and provides
+//   load         the region of query slot r (its record; boxes by row),
+//   shfl         the same region taken from another lane,
+//   wants        which children of a node with split value sv (in the
+//                dimension sel) the region reaches,
+//   process      whether point c counts, and the high word of its list key,
+//   empty_key    the key of an empty list slot,
+//   box_test     a subtree's bounding box disjoint from / inside the region.
+template <int D>
+struct BallQuery {
+    static constexpr bool kBox = false;
+    float q[D];
+    __device__ __forceinline__ void load(const NodeRec<D>& r, const float*) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        if (j >= off) {
-            const uint32_t id = uint32_t(s.L[j]);
-            const bool empty = id == SENT_IDX;
-            oi[j - off] = empty ? -1 : int32_t(id);
-            if (od) od[j - off] = empty ? __builtin_inff() : key_d2(s.L[j]);
-        }
+        for (int j = 0; j < D; ++j) q[j] = r.c[j];
     }
-}
-
-// Which children the query region reaches, at a node of split dimension sel
-// with split value sv.
-template <int D, int K, bool BOXQ>
-__device__ __forceinline__ void range_wants(const RangeLane<D, K, BOXQ>& s, const DimSel<D>& sel, float sv,
-                                            float R2, bool& want_l, bool& want_r) {
-    if constexpr (BOXQ) {
-        const float lo = sel.template rot<0>(s.a);
-        const float hi = sel.template rot<0>(s.b);
-        want_l = lo <= sv;
-        want_r = hi >= sv;
-    } else {
-        const float qd = sel.template rot<0>(s.a);
-        const float sd = qd - sv;
+    __device__ __forceinline__ BallQuery shfl(int src) const {
+        BallQuery o;
+#pragma unroll
+        for (int j = 0; j < D; ++j) o.q[j] = __shfl(q[j], src);
+        return o;
+    }
+    // the left subtree holds coordinates <= sv, the right >= sv: a side is
+    // skipped when the plane lies farther than the radius on the other side
+    __device__ __forceinline__ void wants(const DimSel<D>& sel, float sv, float R2, bool& want_l,
+                                          bool& want_r) const {
+        const float sd = sel.template rot<0>(q) - sv;
         const bool far = sd * sd > R2;
         want_l = !(sd > 0.0f && far);
         want_r = !(sd < 0.0f && far);
     }
-}
-
-// The subtree of node `id` against the query region: disjoint (no point can
-// be in range), or (count-only queries) wholly inside it.
-template <int D, int K, bool BOXQ>
-__device__ __forceinline__ void range_box_test(const RangeLane<D, K, BOXQ>& s, const float* __restrict__ boxes,
-                                               int32_t id, float R2, bool want_inside, bool& disjoint,
-                                               bool& inside) {
-    constexpr int H = box_words(D) / 2;
-    const uint4* p = reinterpret_cast<const uint4*>(boxes + int64_t(id) * box_words(D));
-    float w[8];
-    const uint4 u = p[0];
-    w[0] = __uint_as_float(u.x); w[1] = __uint_as_float(u.y); w[2] = __uint_as_float(u.z); w[3] = __uint_as_float(u.w);
-    if (box_words(D) == 8) {
-        const uint4 v = p[1];
-        w[4] = __uint_as_float(v.x); w[5] = __uint_as_float(v.y); w[6] = __uint_as_float(v.z); w[7] = __uint_as_float(v.w);
-    }
-    if constexpr (BOXQ) {
-        bool out = false, in = true;
+    // squared distance left to right without contraction, as kNN; the list
+    // key is (d2, index)
+    __device__ __forceinline__ bool process(const float (&c)[D], float R2, uint32_t& key_hi) const {
+        float dx[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            out = out | (w[H + j] < s.a[j]) | (w[j] > s.b[j]);
-            in = in & (s.a[j] <= w[j]) & (w[H + j] <= s.b[j]);
-        }
-        disjoint = out;
-        inside = want_inside & in;
-    } else {
+        for (int j = 0; j < D; ++j) dx[j] = q[j] - c[j];
+        float d2 = dx[0] * dx[0];
+#pragma unroll
+        for (int j = 1; j < D; ++j) d2 = d2 + dx[j] * dx[j];
+        key_hi = __float_as_uint(d2);
+        return d2 <= R2;
+    }
+    static __device__ __forceinline__ uint64_t empty_key(float R2) { return make_key(R2, SENT_IDX); }
+    // box lows w[0..D), highs w[H..H+D): the offsets to the nearer and the
+    // farther face bound every point's |fl(q - p)| from below and above
+    template <int H>
+    __device__ __forceinline__ void box_test(const float (&w)[8], float R2, bool want_inside, bool& disjoint,
+                                             bool& inside) const {
         float near[D], far[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            const float below = s.a[j] - w[j];      // >= 0 when q is above the low face
-            const float above = s.a[j] - w[H + j];  // <= 0 when q is below the high face
+            const float below = q[j] - w[j];      // >= 0 when q is above the low face
+            const float above = q[j] - w[H + j];  // <= 0 when q is below the high face
             near[j] = below < 0.0f ? below : (above > 0.0f ? above : 0.0f);
             far[j] = fmaxf(fabsf(below), fabsf(above));
         }
@@ -1950,20 +1930,113 @@ __device__ __forceinline__ void range_box_test(const RangeLane<D, K, BOXQ>& s, c
         disjoint = dmin > R2;
         inside = want_inside & (dmax <= R2);
     }
+};
+
+template <int D>
+struct BoxQuery {
+    static constexpr bool kBox = true;
+    float lo[D], hi[D];
+    __device__ __forceinline__ void load(const NodeRec<D>& r, const float* boxes) {
+        const float* bx = boxes + size_t(r.idx) * 2 * D;  // the caller's box of this row
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            lo[j] = bx[j];
+            hi[j] = bx[D + j];
+        }
+    }
+    __device__ __forceinline__ BoxQuery shfl(int src) const {
+        BoxQuery o;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            o.lo[j] = __shfl(lo[j], src);
+            o.hi[j] = __shfl(hi[j], src);
+        }
+        return o;
+    }
+    __device__ __forceinline__ void wants(const DimSel<D>& sel, float sv, float, bool& want_l, bool& want_r) const {
+        want_l = sel.template rot<0>(lo) <= sv;
+        want_r = sel.template rot<0>(hi) >= sv;
+    }
+    // inside in every dimension, inclusive; the list key is (1, index), above
+    // the spare slots' key 0
+    __device__ __forceinline__ bool process(const float (&c)[D], float, uint32_t& key_hi) const {
+        bool in = true;
+#pragma unroll
+        for (int j = 0; j < D; ++j) in = in & (lo[j] <= c[j]) & (c[j] <= hi[j]);
+        key_hi = 1u;
+        return in;
+    }
+    static __device__ __forceinline__ uint64_t empty_key(float) { return (uint64_t(2) << 32) | SENT_IDX; }
+    template <int H>
+    __device__ __forceinline__ void box_test(const float (&w)[8], float, bool want_inside, bool& disjoint,
+                                             bool& inside) const {
+        bool out = false, in = true;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            out = out | (w[H + j] < lo[j]) | (w[j] > hi[j]);
+            in = in & (lo[j] <= w[j]) & (w[H + j] <= hi[j]);
+        }
+        disjoint = out;
+        inside = want_inside & in;
+    }
+};
+
+template <int D, int K, class Qy>
+struct RangeLane {
+    Qy g;              // the query region
+    uint64_t L[K];
+    int32_t curr, prev, row;
+    uint32_t count, vis;
+};
+
+template <int D, int K, class Qy>
+__device__ __forceinline__ void range_finish(const RangeLane<D, K, Qy>& s, const RangeArgs& a) {
+    a.out_count[s.row] = s.count;
+    if (a.visited) a.visited[s.row] = s.vis;
+    if (a.cap == 0) return;
+    int32_t* oi = a.out_idx + int64_t(s.row) * a.cap;
+    float* od = (!Qy::kBox && a.out_d2) ? a.out_d2 + int64_t(s.row) * a.cap : nullptr;
+    const int off = K - a.cap;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (j >= off) {
+            const uint32_t id = uint32_t(s.L[j]);
+            const bool empty = id == SENT_IDX;
+            oi[j - off] = empty ? -1 : int32_t(id);
+            if (od) od[j - off] = empty ? __builtin_inff() : key_d2(s.L[j]);
+        }
+    }
 }
 
-template <int D, int K, bool BOXQ, bool XD, bool SB>
+// The subtree of node `id` against the query region: disjoint (no point can
+// be in range), or (count-only queries) wholly inside it.
+template <int D, class Qy>
+__device__ __forceinline__ void range_box_test(const Qy& g, const float* __restrict__ boxes, int32_t id, float R2,
+                                               bool want_inside, bool& disjoint, bool& inside) {
+    const uint4* p = reinterpret_cast<const uint4*>(boxes + int64_t(id) * box_words(D));
+    float w[8];
+    const uint4 u = p[0];
+    w[0] = __uint_as_float(u.x); w[1] = __uint_as_float(u.y); w[2] = __uint_as_float(u.z); w[3] = __uint_as_float(u.w);
+    w[4] = w[5] = w[6] = w[7] = 0.0f;
+    if (box_words(D) == 8) {
+        const uint4 v = p[1];
+        w[4] = __uint_as_float(v.x); w[5] = __uint_as_float(v.y); w[6] = __uint_as_float(v.z); w[7] = __uint_as_float(v.w);
+    }
+    g.template box_test<box_words(D) / 2>(w, R2, want_inside, disjoint, inside);
+}
+
+template <int D, int K, class Qy, bool XD, bool SB>
 __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
     const TreeRec<D>* __restrict__ g1 = reinterpret_cast<const TreeRec<D>*>(a.nodes);
     const int32_t* __restrict__ ids = node_ids<D>(g1, a.N);
     const uint32_t lane = __lane_id();
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
     // chunk of 64 query slots held across the wave (lane l: slot cb + l)
-    float ca[D], cbx[BOXQ ? D : 1];
+    Qy chunk;
     int32_t crow = 0;
     uint32_t cb = 0, cn = 0, cpos = 0;
     bool exhausted = false;
-    RangeLane<D, K, BOXQ> s;
+    RangeLane<D, K, Qy> s;
     s.curr = 0;
     for (;;) {
         const uint64_t need = wave_ballot(s.curr == 0);
@@ -1981,17 +2054,7 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
                     if (lane < cn) {
                         const NodeRec<D> r = load_query<D>(static_cast<const NodeRec<D>*>(a.recs) + cb + lane);
                         crow = r.idx;
-                        if constexpr (BOXQ) {
-                            const float* bx = a.boxes + size_t(crow) * 2 * D;
-#pragma unroll
-                            for (int j = 0; j < D; ++j) {
-                                ca[j] = bx[j];
-                                cbx[j] = bx[D + j];
-                            }
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < D; ++j) ca[j] = r.c[j];
-                        }
+                        chunk.load(r, a.boxes);
                     }
                 }
             }
@@ -2000,27 +2063,16 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
                 const uint32_t rank = __popcll(need & lt_mask);
                 const uint32_t take = n < cn - cpos ? n : cn - cpos;
                 const int src = int(cpos + (rank < take ? rank : 0));
-                float va[D], vb[BOXQ ? D : 1];
-#pragma unroll
-                for (int j = 0; j < D; ++j) va[j] = __shfl(ca[j], src);
-                if constexpr (BOXQ) {
-#pragma unroll
-                    for (int j = 0; j < D; ++j) vb[j] = __shfl(cbx[j], src);
-                }
+                const Qy vg = chunk.shfl(src);
                 const int32_t vrow = __shfl(crow, src);
                 if (s.curr == 0 && rank < take) {
-#pragma unroll
-                    for (int j = 0; j < D; ++j) s.a[j] = va[j];
-                    if constexpr (BOXQ) {
-#pragma unroll
-                        for (int j = 0; j < D; ++j) s.b[j] = vb[j];
-                    }
+                    s.g = vg;
                     s.row = vrow;
                     s.count = 0;
                     s.vis = 0;
                     // spare slots (beyond cap) hold key 0 in front; empty
                     // slots the largest key of the list's kind
-                    const uint64_t empty = BOXQ ? ((uint64_t(2) << 32) | SENT_IDX) : make_key(a.R2, SENT_IDX);
+                    const uint64_t empty = Qy::empty_key(a.R2);
 #pragma unroll
                     for (int j = 0; j < K; ++j) s.L[j] = (j < K - a.cap) ? uint64_t(0) : empty;
                     s.curr = 1;
@@ -2042,7 +2094,7 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
             if constexpr (SB) {
                 if (from_parent && curr < a.box_below) {
                     bool disjoint, inside;
-                    range_box_test<D, K, BOXQ>(s, a.sboxes, curr, a.R2, a.cap == 0, disjoint, inside);
+                    range_box_test<D>(s.g, a.sboxes, curr, a.R2, a.cap == 0, disjoint, inside);
                     if (inside) s.count += subtree_size(curr, a.N);
                     skip = disjoint | inside;
                 }
@@ -2050,34 +2102,17 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
             if (from_parent & skip) ++s.vis;  // entered, and left at once
             if (from_parent & !skip) {
                 ++s.vis;
-                bool in;
-                uint64_t key;
-                if constexpr (BOXQ) {
-                    in = true;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) in = in & (s.a[j] <= c[j]) & (c[j] <= s.b[j]);
-                    key = 0;
-                } else {
-                    float dx[D];
-#pragma unroll
-                    for (int j = 0; j < D; ++j) dx[j] = s.a[j] - c[j];
-                    float d2 = dx[0] * dx[0];
-#pragma unroll
-                    for (int j = 1; j < D; ++j) d2 = d2 + dx[j] * dx[j];
-                    in = d2 <= a.R2;
-                    key = uint64_t(__float_as_uint(d2)) << 32;
-                }
-                if (in) {
+                uint32_t key_hi;
+                if (s.g.process(c, a.R2, key_hi)) {
                     ++s.count;
                     const int32_t id = rec_has_idx(D) ? idx : ids[curr];
-                    key |= uint32_t(id);
-                    if (BOXQ) key |= uint64_t(1) << 32;  // above the spare slots' key 0
+                    const uint64_t key = (uint64_t(key_hi) << 32) | uint32_t(id);
                     if (key < s.L[K - 1]) list_insert<K>(s.L, key);
                 }
             }
             const DimSel<D> sel = split_dim<D, XD, 0>(curr, db);
             bool want_l, want_r;
-            range_wants<D, K, BOXQ>(s, sel, sel.template rot<0>(c), a.R2, want_l, want_r);
+            s.g.wants(sel, sel.template rot<0>(c), a.R2, want_l, want_r);
             const int32_t lc = curr << 1, rc = lc | 1;
             int32_t next, nprev = curr;
             if (from_parent && !skip && want_l && lc <= a.N) next = lc;
@@ -2089,7 +2124,7 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
                 next = p;
                 if (p != 0 && (curr & 1) == 0) {
                     bool pl, pr;
-                    range_wants<D, K, BOXQ>(s, split_dim<D, XD, 1>(curr, db), anc[0], a.R2, pl, pr);
+                    s.g.wants(split_dim<D, XD, 1>(curr, db), anc[0], a.R2, pl, pr);
                     if (pr && (curr | 1) <= a.N) {
                         next = curr | 1;
                         nprev = p;
@@ -2107,7 +2142,7 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
             }
             s.prev = nprev;
             s.curr = next;
-            if (next == 0) range_finish<D, K, BOXQ>(s, a);
+            if (next == 0) range_finish<D, K, Qy>(s, a);
         }
     }
 }
@@ -2124,11 +2159,11 @@ template <int D, int K, bool XD>
 void launch_range_kx(const RangeArgs& a, bool box, int grid, hipStream_t st) {
     const dim3 g(grid), b(256);
     if (a.sboxes) {
-        if (box) hipLaunchKernelGGL((range_persistent<D, K, true, XD, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((range_persistent<D, K, false, XD, true>), g, b, 0, st, a);
+        if (box) hipLaunchKernelGGL((range_persistent<D, K, BoxQuery<D>, XD, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((range_persistent<D, K, BallQuery<D>, XD, true>), g, b, 0, st, a);
     } else {
-        if (box) hipLaunchKernelGGL((range_persistent<D, K, true, XD, false>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((range_persistent<D, K, false, XD, false>), g, b, 0, st, a);
+        if (box) hipLaunchKernelGGL((range_persistent<D, K, BoxQuery<D>, XD, false>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((range_persistent<D, K, BallQuery<D>, XD, false>), g, b, 0, st, a);
     }
 }
 

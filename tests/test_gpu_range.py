@@ -290,3 +290,41 @@ def test_radius_box_clustered_1m_sampled(oracle_lib):
     _same_box((bc[rows], bi[rows]), (oc, oi), cap, "gmm64 box")
     assert gc.sum() > 10 * Qs.shape[0] and bc.sum() > Qs.shape[0]  # non-trivial regions
     tree.close()
+
+
+def test_clustered_10m_sampled_rows(oracle_lib):
+    """10M clustered points, 1M queries in one launch per call (radius with
+    cap 16, radius counts with and without subtree boxes, box counts): 400
+    sampled rows against the definitions over the points whose x lies in
+    the query's slab (every point in range is among them)."""
+    P, Qs = datagen.workload("clustered-10m")
+    Qs = Qs[: 1 << 20]
+    tree = _build(P)
+    q = _t(Qs)
+    maxr, cap, h = 0.01, 16, np.float32(0.008)
+    print("[gpu] range clustered-10m: radius and box over 1M queries", flush=True)
+    rc, ri, rd = kd.kd_radius_search(tree, q, maxr, cap)
+    cc, _, _ = kd.kd_radius_search(tree, q, maxr, 0, flags=BOXES)
+    bc, _ = kd.kd_box_search(tree, _t(Qs - h), _t(Qs + h), 0, flags=BOXES)
+    bp, _ = kd.kd_box_search(tree, _t(Qs - h), _t(Qs + h), 0)
+    torch.cuda.synchronize()
+    rc, ri, rd = rc.cpu().numpy(), ri.cpu().numpy(), rd.cpu().numpy()
+    cc, bc, bp = cc.cpu().numpy(), bc.cpu().numpy(), bp.cpu().numpy()
+    assert np.array_equal(rc, cc) and np.array_equal(bc, bp)
+    order = np.argsort(P[:, 0], kind="stable")
+    xs = P[order, 0].astype(np.float64)
+    rows = np.random.default_rng(13).choice(len(Qs), 400, replace=False)
+    print("[gpu] range clustered-10m: definitions on 400 sampled rows", flush=True)
+    for row in rows:
+        x = float(Qs[row, 0])
+        r = maxr * (1 + 1e-5) + 1e-12
+        cand = np.sort(order[np.searchsorted(xs, x - r, "left"):np.searchsorted(xs, x + r, "right")])
+        oc, oi, od = oracle_lib.radius(P[cand], Qs[row][None, :], maxr, cap)
+        oi = np.where(oi[0] >= 0, cand[np.maximum(oi[0], 0)], -1)
+        assert rc[row] == oc[0] and np.array_equal(ri[row], oi), f"radius row {row}"
+        assert np.array_equal(rd[row].view(np.uint32), od[0].view(np.uint32)), f"radius d2 row {row}"
+        lo, hi = Qs[row] - h, Qs[row] + h
+        cand = np.sort(order[np.searchsorted(xs, float(lo[0]), "left"):np.searchsorted(xs, float(hi[0]), "right")])
+        ob, _ = oracle_lib.box(P[cand], lo[None, :], hi[None, :], 0)
+        assert bc[row] == ob[0], f"box row {row}"
+    tree.close()
