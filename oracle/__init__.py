@@ -10,7 +10,7 @@ Contents
     dimension by level, or stored per node: the widest extent), the ordered
     recursive traversal of the paper's Sec. 3.1, brute force, the
     learned-radius rule, radius and box queries by their plain definitions
-    (the "find all points within a radius / inside a box" variants of Sec. 3),
+    (the sphere and box query variants that Sec. 3 names),
     threaded batch drivers.
   * ``mlp_ref``: float64 reference of the radius-prediction MLP with the
     bfloat16 rounding points of the GPU kernels emulated.

@@ -106,7 +106,8 @@ static int cmp_by_dim(const void* a, const void* b) {
 }
 
 /* Dimension of largest extent fl32(max - min) over the n >= 1 points S[0..n),
- * the lowest dimension among equal extents. */
+ * the lowest dimension among equal extents (the builder's choice of split
+ * dimension, stored per node: Sec. 3 assumption list, Sec. 4). */
 static int widest_dim(const float* P, int D, const int32_t* S, int64_t n) {
     int best = 0;
     float best_ext = -1.0f;
@@ -297,8 +298,10 @@ void oracle_brute_one(const float* P, int64_t N, int D, const float* q, int k, f
 
 /* -------------------------------------------------- range queries (brute) */
 
-/* All points within the radius (d2 <= R2, the definition above): returns
- * their number; the k smallest of them by (d2, caller index) go to
+/* All points within the radius (Sec. 3 names sphere and box query primitives
+ * and un-ordered traversals as variants of the method; d2 <= R2 as defined
+ * above):
+ * returns their number; the k smallest of them by (d2, caller index) go to
  * out_idx / out_d2 as in oracle_brute_one (k = 0: count only). */
 int64_t oracle_radius_one(const float* P, int64_t N, int D, const float* q, float R2, int k,
                           int32_t* out_idx, float* out_d2) {
@@ -309,8 +312,9 @@ int64_t oracle_radius_one(const float* P, int64_t N, int D, const float* q, floa
     return count;
 }
 
-/* All points inside the axis-aligned box [lo, hi] (lo[j] <= p[j] <= hi[j] in
- * every dimension, inclusive): returns their number; the k smallest caller
+/* All points inside the axis-aligned box [lo, hi] (Sec. 3: a box as the
+ * query primitive; lo[j] <= p[j] <= hi[j] in every dimension, inclusive):
+ * returns their number; the k smallest caller
  * indices of them, ascending, go to out_idx, -1 after them (k = 0: count
  * only).  Scanning indices upwards, the first k found are the smallest. */
 int64_t oracle_box_one(const float* P, int64_t N, int D, const float* lo, const float* hi, int k,

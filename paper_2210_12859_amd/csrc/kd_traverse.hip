@@ -1803,8 +1803,9 @@ kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& p
 // ------------------------------------------------------------ range queries
 //
 // All points within a radius of a query, or inside an axis-aligned box: the
-// un-ordered form of the same state machine (Sec. 3 calls it a trivial
-// simplification): children in fixed order, left then right, each entered
+// un-ordered form of the same state machine (Sec. 3 treats the un-ordered
+// traversal and other query shapes as easy variants of the ordered point
+// query): children in fixed order, left then right, each entered
 // only when the query region can reach its half-space.  The left subtree of a
 // node holds coordinates <= its split value s in the split dimension, the
 // right subtree coordinates >= s, so
