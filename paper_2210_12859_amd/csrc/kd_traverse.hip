@@ -1,4 +1,6 @@
-// kd_traverse.hip -- stack-free fcp / kNN traversal kernels for gfx950.
+// kd_traverse.hip -- stack-free fcp / kNN traversal kernels for gfx950, the
+// cooperative hand-off, the batched and learned-radius variants, and the
+// un-ordered range-query kernels (radius and box search, end of file).
 //
 // Each lane runs the two-integer state machine of the paper's Sec. 3.2 for
 // one query: `curr` and `prev` alone decide where to go next.
@@ -23,8 +25,12 @@
 //   * a step onto a child that does not exist (id > N) and the bounce back
 //     are resolved in place: the next node is the one the bounce would pick;
 //   * a "return to parent" step is resolved with the parent's split value
-//     stored in the current node's record (KD_FUSED_LEVELS = 1 level), so a
-//     lane does not reload its parent to learn which child it came from.
+//     stored in the current node's record (one level for D = 2 and 3, three
+//     ancestors for D = 4), so a lane does not reload its parent to learn
+//     which child it came from.
+// The split dimension of a node is its level's (floor(log2 id) mod D), or,
+// for trees that store it (the XD kernels), read from a byte per node that
+// also holds the dimensions of its three nearest ancestors.
 // The processed-node sequence therefore equals the paper's, and the ordered
 // recursion's, node for node.
 //
