@@ -35,6 +35,7 @@ struct kd_batch_s {
         int n_mlp = 0;
         uint32_t mlp_tiles = 0;
         kd::QueryPlan plan;
+        float est_ms = 0.0f;             // expected pipeline time: measured by the autotuner, else estimated
     };
     std::vector<Class> classes;
     std::vector<std::pair<int32_t*, float*>> empty_out;  // jobs over empty trees
@@ -118,6 +119,25 @@ ClassLayout class_layout(const kd_batch_s::Class& c, int device) {
     return L;
 }
 
+// Rough time of a group's pipeline, from the measured single-tree cost per
+// query on 1M-point trees (fcp 0.25 ms, k = 8 0.67 ms, k = 64 6.4 ms per 1M
+// 3-D queries; 4-D about 1.7x, 2-D 0.7x).  Only the order in which the groups
+// are captured depends on it.
+float class_cost_estimate(int dim, int K, uint32_t n) {
+    float kf = 1.0f;
+    switch (K) {
+        case 1: kf = 0.37f; break;
+        case 2: kf = 0.5f; break;
+        case 4: kf = 0.65f; break;
+        case 8: kf = 1.0f; break;
+        case 16: kf = 1.9f; break;
+        case 32: kf = 3.8f; break;
+        default: kf = 9.5f; break;
+    }
+    const float df = dim == 2 ? 0.7f : (dim == 3 ? 1.0f : 1.7f);
+    return float(n) * 0.67e-6f * kf * df;
+}
+
 // The whole pipeline of one class on stream st.
 kd_status enqueue_class(const kd_batch_s::Class& c, int device, hipStream_t st) {
     const ClassLayout L = class_layout(c, device);
@@ -186,11 +206,18 @@ kd_status capture_batch(kd_batch b, hipStream_t cs_in) {
                            b->empty_out[i].first, b->empty_out[i].second, n);
     }
     kd_status s = KD_OK;
+    // longest groups first: the branches start in capture order and share the
+    // device's few hardware queues, so a long group captured last would run
+    // alone at the end
+    std::vector<size_t> order(b->classes.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return b->classes[x].est_ms > b->classes[y].est_ms; });
     e = hipEventRecord(fork, cs);
     for (size_t i = 0; i < b->classes.size() && s == KD_OK && e == hipSuccess; ++i) {
         e = hipStreamWaitEvent(side[i], fork, 0);
         if (e != hipSuccess) break;
-        s = enqueue_class(b->classes[i], b->device, side[i]);
+        s = enqueue_class(b->classes[order[i]], b->device, side[i]);
         if (s != KD_OK) break;
         e = hipEventRecord(done[i], side[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[i], 0);
@@ -315,6 +342,7 @@ kd_status kd_batch_create(const kd_job* jobs, int n_jobs, kd_model model, const 
             while ((1 << jb) < c.njobs) ++jb;
             c.plan.sort_bits = std::min(32, ((jb + 16 + 7) / 8) * 8);
         }
+        c.est_ms = class_cost_estimate(c.dim, c.K, c.n);
         b->classes.push_back(c);  // owned (freed on error) from here on
         kd_batch_s::Class& cc = b->classes.back();
         KD_HIP(hipMalloc(&cc.d_jobs, kv.second.size() * sizeof(BatchJob)));
@@ -437,6 +465,7 @@ kd_status kd_batch_autotune(kd_batch b, int reps, kd_stream stream, kd_opts* cla
             if (s != KD_OK) break;
         }
         c.plan = s == KD_OK ? best : keep;
+        if (s == KD_OK) c.est_ms = best_ms / float(reps);
         if (s != KD_OK) break;
     }
     if (s == KD_OK) s = capture_batch(b, reinterpret_cast<hipStream_t>(stream));
