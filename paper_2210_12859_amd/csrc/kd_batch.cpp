@@ -119,6 +119,10 @@ ClassLayout class_layout(const kd_batch_s::Class& c, int device) {
     return L;
 }
 
+#ifndef KD_BATCH_BRANCHES
+#define KD_BATCH_BRANCHES 3
+#endif
+
 // Rough time of a group's pipeline, from the measured single-tree cost per
 // query on 1M-point trees (fcp 0.25 ms, k = 8 0.67 ms, k = 64 6.4 ms per 1M
 // 3-D queries; 4-D about 1.7x, 2-D 0.7x).  Only the order in which the groups
@@ -175,8 +179,25 @@ kd_status capture_batch(kd_batch b, hipStream_t cs_in) {
         KD_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
         cs = own;
     }
-    std::vector<hipStream_t> side(b->classes.size(), nullptr);
-    std::vector<hipEvent_t> done(b->classes.size(), nullptr);
+    // The groups run on a few graph branches, each a chain of groups: longest
+    // group first onto the least loaded branch (by expected time).  The
+    // branches share the device's hardware queues, so more branches than
+    // queues would only serialize behind each other in an order the runtime
+    // picks.
+    const size_t nb = std::min<size_t>(b->classes.size(), KD_BATCH_BRANCHES);
+    std::vector<size_t> order(b->classes.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return b->classes[x].est_ms > b->classes[y].est_ms; });
+    std::vector<std::vector<size_t>> chain(nb);
+    std::vector<float> load(nb, 0.0f);
+    for (size_t i : order) {
+        const size_t j = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+        chain[j].push_back(i);
+        load[j] += b->classes[i].est_ms;
+    }
+    std::vector<hipStream_t> side(nb, nullptr);
+    std::vector<hipEvent_t> done(nb, nullptr);
     hipEvent_t fork = nullptr;
     auto release = [&]() {
         for (hipStream_t x : side)
@@ -206,18 +227,14 @@ kd_status capture_batch(kd_batch b, hipStream_t cs_in) {
                            b->empty_out[i].first, b->empty_out[i].second, n);
     }
     kd_status s = KD_OK;
-    // longest groups first: the branches start in capture order and share the
-    // device's few hardware queues, so a long group captured last would run
-    // alone at the end
-    std::vector<size_t> order(b->classes.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t x, size_t y) { return b->classes[x].est_ms > b->classes[y].est_ms; });
     e = hipEventRecord(fork, cs);
-    for (size_t i = 0; i < b->classes.size() && s == KD_OK && e == hipSuccess; ++i) {
+    for (size_t i = 0; i < nb && s == KD_OK && e == hipSuccess; ++i) {
         e = hipStreamWaitEvent(side[i], fork, 0);
         if (e != hipSuccess) break;
-        s = enqueue_class(b->classes[order[i]], b->device, side[i]);
+        for (size_t c : chain[i]) {
+            s = enqueue_class(b->classes[c], b->device, side[i]);
+            if (s != KD_OK) break;
+        }
         if (s != KD_OK) break;
         e = hipEventRecord(done[i], side[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[i], 0);
