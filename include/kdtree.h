@@ -284,6 +284,27 @@ kd_status kd_radius_search(kd_tree t, const float* queries, int64_t Q, float max
 kd_status kd_box_search(kd_tree t, const float* boxes, int64_t Q, int cap, int32_t* out_idx,
                         uint32_t* out_count, uint32_t* visited, int flags, kd_stream stream);
 
+/* Every point in range of every query, as one variable-length result:
+ * query q's points are out_idx[offsets[q] .. offsets[q + 1]), caller
+ * indices in the order the traversal reaches them (deterministic for a given
+ * tree and query).  Two traversals: counts (with subtree boxes when flags
+ * has KD_RANGE_BOXES), an exclusive scan into offsets, then, when the total
+ * fits capacity, the indices (split planes only).
+ *   queries / boxes, maxRadius : as kd_radius_search / kd_box_search.
+ *   offsets  : device int64 [Q + 1]; always written (offsets[Q] = total).
+ *   out_idx  : device int32 [capacity], or NULL with capacity 0.
+ *   capacity : >= 0.  When the total exceeds it, only offsets and *total
+ *              are written (call again with a larger out_idx).
+ *   total    : HOST int64: the number of points in range over all queries.
+ * Synchronises the stream (the total is read back); the call allocates and
+ * frees two small device buffers (4 bytes per query, 8 per 4,096 queries). */
+kd_status kd_radius_search_all(kd_tree t, const float* queries, int64_t Q, float maxRadius,
+                               int64_t* offsets, int32_t* out_idx, int64_t capacity, int64_t* total,
+                               int flags, kd_stream stream);
+kd_status kd_box_search_all(kd_tree t, const float* boxes, int64_t Q, int64_t* offsets,
+                            int32_t* out_idx, int64_t capacity, int64_t* total, int flags,
+                            kd_stream stream);
+
 /* ------------------------------------------------- learned initial radius */
 
 /* A small MLP (3 -> 64 -> 64 -> 1, ReLU; bfloat16 operands, float32

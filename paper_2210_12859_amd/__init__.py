@@ -78,6 +78,8 @@ def lib():
         "kd_knn_noalloc": ([P, P, i64, i32, f32, P, P, P], i32),
         "kd_radius_search": ([P, P, i64, f32, i32, P, P, P, P, i32, P], i32),
         "kd_box_search": ([P, P, i64, i32, P, P, P, i32, P], i32),
+        "kd_radius_search_all": ([P, P, i64, f32, P, P, i64, P, i32, P], i32),
+        "kd_box_search_all": ([P, P, i64, P, P, i64, P, i32, P], i32),
         "kd_radius_model_train": ([P, P, i64, i32, P, P, P], i32),
         "kd_knn_learned": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
         "kd_knn_with_radius": ([P, P, P, i64, i32, f32, P, P, P, P, P, P], i32),
@@ -329,6 +331,48 @@ def kd_box_search(tree: Tree, lo, hi, cap=0, visited=None, flags=0, stream=None)
     _check(lib().kd_box_search(tree.handle, _ptr(boxes), Q, int(cap), _ptr(idx), _ptr(count), _ptr(visited),
                                int(flags), _stream_handle(stream)))
     return count, idx
+
+
+def _range_all(call, Q, dev, capacity):
+    import torch
+    offsets = torch.empty(Q + 1, dtype=torch.int64, device=dev)
+    cap = int(capacity) if capacity is not None else max(1024, 16 * Q)
+    out = torch.empty(cap, dtype=torch.int32, device=dev)
+    total = ctypes.c_int64()
+    _check(call(offsets, out, cap, total))
+    if total.value > cap:
+        cap = total.value
+        out = torch.empty(cap, dtype=torch.int32, device=dev)
+        _check(call(offsets, out, cap, total))
+    return offsets, out[: total.value]
+
+
+def kd_radius_search_all(tree: Tree, queries, max_radius, flags=0, capacity=None, stream=None):
+    """Every point within max_radius of each query: (offsets int64 [Q + 1],
+    idx int32 [total]); query q's points are idx[offsets[q]:offsets[q + 1]]."""
+    import torch
+    _require(queries, torch.float32, "queries")
+    Q = queries.shape[0]
+    sh = _stream_handle(stream)
+    call = lambda off, out, cap, tot: lib().kd_radius_search_all(
+        tree.handle, _ptr(queries), Q, float(max_radius), _ptr(off), _ptr(out), cap, ctypes.byref(tot), int(flags), sh)
+    return _range_all(call, Q, queries.device, capacity)
+
+
+def kd_box_search_all(tree: Tree, lo, hi, flags=0, capacity=None, stream=None):
+    """Every point inside the boxes [lo, hi] (inclusive): (offsets, idx) as
+    kd_radius_search_all."""
+    import torch
+    _require(lo, torch.float32, "lo")
+    _require(hi, torch.float32, "hi")
+    if lo.shape != hi.shape:
+        raise ValueError("lo and hi must have the same shape")
+    boxes = torch.stack([lo, hi], dim=1).contiguous()
+    Q = lo.shape[0]
+    sh = _stream_handle(stream)
+    call = lambda off, out, cap, tot: lib().kd_box_search_all(
+        tree.handle, _ptr(boxes), Q, _ptr(off), _ptr(out), cap, ctypes.byref(tot), int(flags), sh)
+    return _range_all(call, Q, lo.device, capacity)
 
 
 def kd_knn_ex(tree: Tree, queries, k, max_radius=math.inf, out_idx=None, out_d2=None, visited=None,

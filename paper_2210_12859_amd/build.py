@@ -37,6 +37,7 @@ SOURCES = [
     ("kd_autotune.cpp", True, []),
     ("kd_noalloc.hip", True, []),
     ("kd_build_gpu.hip", True, []),
+    ("kd_range_all.hip", True, []),
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",

@@ -258,10 +258,12 @@ struct FixedScratch {
 // [Q][2][dim] boxes.  Writes out_count[Q] and, for cap > 0, out_idx[Q][cap]
 // (and out_d2[Q][cap] for radius queries when given), and visited[Q] (the
 // entered nodes) when given.  Q >= 1, N >= 1.  planes_only: no subtree box
-// tests (split planes only).
+// tests (split planes only).  Fill mode (fill_idx non-NULL; cap 0 and
+// planes_only): every point in range of caller row r is also written to
+// fill_idx[fill_off[r] + its rank in traversal order].
 kd_status run_range(kd_tree t, const float* queries_or_boxes, int64_t Q, bool box, float R2, int cap,
                     int32_t* out_idx, float* out_d2, uint32_t* out_count, uint32_t* visited, bool planes_only,
-                    kd_stream stream);
+                    kd_stream stream, const int64_t* fill_off = nullptr, int32_t* fill_idx = nullptr);
 kd_status run_knn(kd_tree t, const float* queries, int64_t Q, const QueryPlan& plan, int32_t* out_idx,
                   float* out_d2, uint32_t* visited, kd_stream stream, const LearnedSpec* learned = nullptr,
                   kd_stats* stats = nullptr, const FixedScratch* fixed = nullptr);

@@ -1866,6 +1866,8 @@ struct RangeArgs {
     uint32_t* out_count;    // [Q]
     uint32_t* visited;      // [Q] entered nodes, or NULL
     uint32_t* counter;      // chunk cursor, zero at launch
+    const int64_t* fill_off;  // fill mode: first output slot of each caller row
+    int32_t* fill_idx;        // fill mode: every point in range, at fill_off[row] + its rank (NULL: off)
 };
 
 // The two query kinds as compile-time policies of one kernel: the paper's
@@ -1994,6 +1996,7 @@ struct RangeLane {
     uint64_t L[K];
     int32_t curr, prev, row;
     uint32_t count, vis;
+    int64_t base, end; // fill mode: the row's output slots [base, end)
 };
 
 template <int D, int K, class Qy>
@@ -2077,6 +2080,8 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
                     s.row = vrow;
                     s.count = 0;
                     s.vis = 0;
+                    s.base = a.fill_idx ? a.fill_off[vrow] : 0;
+                    s.end = a.fill_idx ? a.fill_off[vrow + 1] : 0;
                     // spare slots (beyond cap) hold key 0 in front; empty
                     // slots the largest key of the list's kind
                     const uint64_t empty = Qy::empty_key(a.R2);
@@ -2111,8 +2116,9 @@ __global__ __launch_bounds__(256) void range_persistent(RangeArgs a) {
                 ++s.vis;
                 uint32_t key_hi;
                 if (s.g.process(c, a.R2, key_hi)) {
-                    ++s.count;
                     const int32_t id = rec_has_idx(D) ? idx : ids[curr];
+                    if (a.fill_idx && s.base + s.count < s.end) a.fill_idx[s.base + s.count] = id;
+                    ++s.count;
                     const uint64_t key = (uint64_t(key_hi) << 32) | uint32_t(id);
                     if (key < s.L[K - 1]) list_insert<K>(s.L, key);
                 }
@@ -2199,7 +2205,7 @@ hipError_t launch_range(int K, const RangeArgs& a, bool box, int grid, hipStream
 
 kd_status run_range(kd_tree t, const float* queries_or_boxes, int64_t Q, bool box, float R2, int cap,
                     int32_t* out_idx, float* out_d2, uint32_t* out_count, uint32_t* visited, bool planes_only,
-                    kd_stream stream) {
+                    kd_stream stream, const int64_t* fill_off, int32_t* fill_idx) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const DeviceInfo& dev = device_info(t->device);
     const int sort_bits = 16;
@@ -2249,6 +2255,8 @@ kd_status run_range(kd_tree t, const float* queries_or_boxes, int64_t Q, bool bo
     a.out_count = out_count;
     a.visited = visited;
     a.counter = counter;
+    a.fill_off = fill_off;
+    a.fill_idx = fill_idx;
     const int K = cap > 0 ? k_template(cap) : 1;
     int64_t grid = int64_t(dev.cus) * 6;  // 24 waves per CU
     const int64_t need = (Q + 255) / 256;

@@ -89,6 +89,27 @@ def test_range_validation():
     assert "tree is NULL" in L.kd_last_error().decode()
 
 
+def test_range_all_validation():
+    L = kd.lib()
+    tot = ctypes.c_int64()
+    off = P(8)
+    # radius: total NULL, Q, flags, radius, capacity, out_idx, tree
+    assert L.kd_radius_search_all(None, P(8), 4, 1.0, off, P(8), 10, None, 0, None) == kd.KD_EINVAL
+    assert "total is NULL" in L.kd_last_error().decode()
+    assert L.kd_radius_search_all(None, P(8), -1, 1.0, off, P(8), 10, ctypes.byref(tot), 0, None) == kd.KD_EINVAL
+    assert L.kd_radius_search_all(None, P(8), 4, 1.0, off, P(8), 10, ctypes.byref(tot), 4, None) == kd.KD_EINVAL
+    assert "unknown flags" in L.kd_last_error().decode()
+    assert L.kd_radius_search_all(None, P(8), 4, -1.0, off, P(8), 10, ctypes.byref(tot), 0, None) == kd.KD_EINVAL
+    assert L.kd_radius_search_all(None, P(8), 4, 1.0, off, P(8), -1, ctypes.byref(tot), 0, None) == kd.KD_EINVAL
+    assert "capacity" in L.kd_last_error().decode()
+    assert L.kd_radius_search_all(None, P(8), 4, 1.0, off, None, 10, ctypes.byref(tot), 0, None) == kd.KD_EINVAL
+    assert "out_idx is NULL" in L.kd_last_error().decode()
+    assert L.kd_radius_search_all(None, P(8), 4, 1.0, off, None, 0, ctypes.byref(tot), 0, None) == kd.KD_EINVAL
+    assert "tree is NULL" in L.kd_last_error().decode()
+    assert L.kd_box_search_all(None, P(8), 4, off, None, 0, ctypes.byref(tot), 0, None) == kd.KD_EINVAL
+    assert "tree is NULL" in L.kd_last_error().decode()
+
+
 def test_build_validation():
     L = kd.lib()
     h = ctypes.c_void_p()

@@ -328,3 +328,75 @@ def test_clustered_10m_sampled_rows(oracle_lib):
         ob, _ = oracle_lib.box(P[cand], lo[None, :], hi[None, :], 0)
         assert bc[row] == ob[0], f"box row {row}"
     tree.close()
+
+
+def _all_same(offsets, idx, want_lists, ctx):
+    off = offsets.cpu().numpy()
+    got = idx.cpu().numpy()
+    assert off[0] == 0 and off[-1] == len(got), ctx
+    for q, w in enumerate(want_lists):
+        g = np.sort(got[off[q]:off[q + 1]])
+        assert np.array_equal(g, np.sort(w)), f"{ctx}: query {q} gpu {len(g)} oracle {len(w)}"
+
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+def test_all_results(oracle_lib, D):
+    """Every point in range, variable-length output: each query's slice holds
+    exactly the definition's points (compared as sets: the order is the
+    traversal's), with and without subtree boxes in the counting pass."""
+    rng = np.random.default_rng(30 + D)
+    P = rng.random((20_000, D), dtype=np.float32)
+    P[:500] = P[500:1000]  # duplicates
+    Qs = rng.random((3_000, D), dtype=np.float32)
+    Qs[5] = np.nan
+    tree = _build(P)
+    maxr = {2: 0.03, 3: 0.08, 4: 0.15}[D]
+    h = np.float32({2: 0.03, 3: 0.07, 4: 0.12}[D])
+    oc, _, _ = oracle_lib.radius(P, Qs, maxr, 0)
+    kmax = int(oc.max())
+    _, oi, _ = oracle_lib.radius(P, Qs, maxr, kmax)
+    want = [oi[q][oi[q] >= 0] for q in range(len(Qs))]
+    bc, _ = oracle_lib.box(P, Qs - h, Qs + h, 0)
+    _, bi = oracle_lib.box(P, Qs - h, Qs + h, int(bc.max()))
+    bwant = [bi[q][bi[q] >= 0] for q in range(len(Qs))]
+    for flags in (0, BOXES):
+        print(f"[gpu] range all D={D} flags={flags}", flush=True)
+        off, idx = kd.kd_radius_search_all(tree, _t(Qs), maxr, flags=flags)
+        torch.cuda.synchronize()
+        _all_same(off, idx, want, f"radius D={D} flags={flags}")
+        off, idx = kd.kd_box_search_all(tree, _t(Qs - h), _t(Qs + h), flags=flags)
+        torch.cuda.synchronize()
+        _all_same(off, idx, bwant, f"box D={D} flags={flags}")
+    tree.close()
+
+
+def test_all_results_capacity_and_empty():
+    dev = _dev()
+    rng = np.random.default_rng(40)
+    P = rng.random((5_000, 3), dtype=np.float32)
+    Qs = rng.random((700, 3), dtype=np.float32)
+    tree = _build(P)
+    q = _t(Qs)
+    L = kd.lib()
+    import ctypes
+    offsets = torch.empty(len(Qs) + 1, dtype=torch.int64, device=dev)
+    out = torch.full((8,), -7, dtype=torch.int32, device=dev)
+    tot = ctypes.c_int64()
+    st = torch.cuda.current_stream().cuda_stream
+    rc = L.kd_radius_search_all(tree.handle, ctypes.c_void_p(q.data_ptr()), len(Qs), 0.1,
+                                ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(out.data_ptr()), 8,
+                                ctypes.byref(tot), 0, ctypes.c_void_p(st))
+    assert rc == kd.KD_OK and tot.value > 8
+    assert offsets[-1].item() == tot.value and (out == -7).all()  # too small: indices untouched
+    c, _, _ = kd.kd_radius_search(tree, q, 0.1, 0)
+    assert np.array_equal(np.diff(offsets.cpu().numpy()), c.cpu().numpy().astype(np.int64))
+    # exact capacity, then empty query sets and an empty tree
+    off2, idx2 = kd.kd_radius_search_all(tree, q, 0.1, capacity=tot.value)
+    assert len(idx2) == tot.value and torch.equal(off2, offsets)
+    off3, idx3 = kd.kd_radius_search_all(tree, q[:0], 0.1)
+    assert off3.tolist() == [0] and idx3.numel() == 0
+    tree.close()
+    empty = kd.kd_build(torch.zeros((0, 3), dtype=torch.float32, device=dev))
+    off4, idx4 = kd.kd_box_search_all(empty, q - 1, q + 1)
+    assert (off4 == 0).all() and idx4.numel() == 0
+    empty.close()
