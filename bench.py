@@ -460,6 +460,49 @@ def range_queries(args):
                 f"oracle {cell['cpu_baseline']['value'] / 1e3:.1f} K q/s; "
                 f"exact {pl['exact_on_sample'] and df['exact_on_sample']}")
             cells.append(cell)
+        # every point in range (offsets + indices): counting pass, scan, fill
+        import ctypes
+        L = kd.lib()
+        st = ctypes.c_void_p(stream.cuda_stream)
+        # (uniform data only: the same region sizes hold ~10^4 clustered
+        # points each, 10^10 results over 1M queries)
+        for kind, m in ((("radius", 64), ("box", 64)) if wl == "uniform-1m" else ()):
+            if kind == "radius":
+                size = (3.0 * m / (4.0 * math.pi * N)) ** (1.0 / 3.0)
+                src = q
+            else:
+                size = 0.5 * (m / N) ** (1.0 / 3.0)
+                src = torch.stack([torch.from_numpy(Qs - np.float32(size)), torch.from_numpy(Qs + np.float32(size))],
+                                  dim=1).contiguous().to(dev)
+            off = torch.empty(Q + 1, dtype=torch.int64, device=dev)
+            tot = ctypes.c_int64()
+
+            def run_all(out, cap):
+                if kind == "radius":
+                    rc = L.kd_radius_search_all(tree.handle, ctypes.c_void_p(src.data_ptr()), Q, size,
+                                                ctypes.c_void_p(off.data_ptr()), ctypes.c_void_p(out), cap,
+                                                ctypes.byref(tot), 0, st)
+                else:
+                    rc = L.kd_box_search_all(tree.handle, ctypes.c_void_p(src.data_ptr()), Q,
+                                             ctypes.c_void_p(off.data_ptr()), ctypes.c_void_p(out), cap,
+                                             ctypes.byref(tot), 0, st)
+                assert rc == 0, L.kd_last_error().decode()
+
+            run_all(None, 0)
+            out = torch.empty(max(1, tot.value), dtype=torch.int32, device=dev)
+            for _ in range(max(1, args.warmup)):
+                run_all(out.data_ptr(), tot.value)
+            t0 = time.perf_counter()
+            reps = max(1, args.steps // 2)
+            for _ in range(reps):
+                run_all(out.data_ptr(), tot.value)
+            ms = (time.perf_counter() - t0) * 1e3 / reps  # the call synchronises
+            cell = {"workload": wl, "kind": kind + "_all", "size": size, "total_results": tot.value,
+                    "qps": Q / (ms / 1e3), "results_per_s": tot.value / (ms / 1e3), "ms_per_call": ms}
+            log(f"{wl} {kind} all results size={size:.4g}: {tot.value} results, {ms:.3f} ms/call, "
+                f"{cell['qps'] / 1e6:.1f} M q/s, {cell['results_per_s'] / 1e9:.2f} G results/s")
+            cells.append(cell)
+            del out, off, src
         tree.close()
     print(json.dumps({"range_queries": cells, "steps": args.steps, "warmup": args.warmup,
                       "note": "radius: ball of radius size; box: cube of half-width size around each query"}),
