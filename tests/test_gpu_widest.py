@@ -141,6 +141,19 @@ def test_range_queries(oracle_lib):
         bc, _ = kd.kd_box_search(tree, _t(Qs - h), _t(Qs + h), 0, flags=flags)
         torch.cuda.synchronize()
         assert np.array_equal(c.cpu().numpy(), orc) and np.array_equal(bc.cpu().numpy(), oc)
+    # rows kept with subtree boxes (disjoint subtrees skipped)
+    c, i, d = kd.kd_radius_search(tree, _t(Qs), 0.2, 16, flags=kd.KD_RANGE_BOXES)
+    torch.cuda.synchronize()
+    orc2, ori2, ord2 = oracle_lib.radius(P, Qs, 0.2, 16)
+    assert np.array_equal(c.cpu().numpy(), orc2) and np.array_equal(i.cpu().numpy(), ori2)
+    assert np.array_equal(d.cpu().numpy().view(np.uint32), ord2.view(np.uint32))
+    # every point in range, as offsets + indices
+    off, idx = kd.kd_box_search_all(tree, _t(Qs - h), _t(Qs + h))
+    torch.cuda.synchronize()
+    off, idx = off.cpu().numpy(), idx.cpu().numpy()
+    _, oall = oracle_lib.box(P, Qs - h, Qs + h, int(oc.max()))
+    for q in range(len(Qs)):
+        assert np.array_equal(np.sort(idx[off[q]:off[q + 1]]), oall[q][oall[q] >= 0]), f"box all, query {q}"
     tree.close()
 
 
