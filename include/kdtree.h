@@ -296,8 +296,9 @@ kd_status kd_box_search(kd_tree t, const float* boxes, int64_t Q, int cap, int32
  *   capacity : >= 0.  When the total exceeds it, only offsets and *total
  *              are written (call again with a larger out_idx).
  *   total    : HOST int64: the number of points in range over all queries.
- * Synchronises the stream (the total is read back); the call allocates and
- * frees two small device buffers (4 bytes per query, 8 per 4,096 queries). */
+ * Synchronises the stream (the total is read back).  Beside the per-stream
+ * workspace of the query calls, the library keeps a second per-stream buffer
+ * for the counts (4 bytes per query, grown on demand, kept until exit). */
 kd_status kd_radius_search_all(kd_tree t, const float* queries, int64_t Q, float maxRadius,
                                int64_t* offsets, int32_t* out_idx, int64_t capacity, int64_t* total,
                                int flags, kd_stream stream);

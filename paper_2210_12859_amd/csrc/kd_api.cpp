@@ -29,6 +29,7 @@ struct ScratchBuf {
 };
 std::mutex g_scratch_mu;
 std::map<std::pair<int, kd_stream>, ScratchBuf> g_scratch;
+std::map<std::pair<int, kd_stream>, ScratchBuf> g_aux_scratch;
 }  // namespace
 
 kd_status set_error(kd_status s, const std::string& msg) {
@@ -87,11 +88,13 @@ kd_status timing_end(hipStream_t st, hipEvent_t ev0, const char* kernel) {
     return KD_OK;
 }
 
-kd_status scratch(kd_stream stream, size_t bytes, void** out) {
+namespace {
+kd_status grow_scratch(std::map<std::pair<int, kd_stream>, ScratchBuf>& m, kd_stream stream, size_t bytes,
+                       void** out) {
     int dev = 0;
     KD_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_scratch_mu);
-    ScratchBuf& b = g_scratch[{dev, stream}];
+    ScratchBuf& b = m[{dev, stream}];
     if (b.bytes < bytes) {
         if (b.ptr) {
             // the stream may still use the old buffer
@@ -106,6 +109,13 @@ kd_status scratch(kd_stream stream, size_t bytes, void** out) {
     }
     *out = b.ptr;
     return KD_OK;
+}
+}  // namespace
+
+kd_status scratch(kd_stream stream, size_t bytes, void** out) { return grow_scratch(g_scratch, stream, bytes, out); }
+
+kd_status aux_scratch(kd_stream stream, size_t bytes, void** out) {
+    return grow_scratch(g_aux_scratch, stream, bytes, out);
 }
 
 namespace {

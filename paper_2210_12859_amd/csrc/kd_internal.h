@@ -135,6 +135,9 @@ const DeviceInfo& device_info(int device);
 // Returns a device buffer of at least `bytes`, private to (device, stream).
 // Calls on one stream are ordered, so reuse across calls is safe.
 kd_status scratch(kd_stream stream, size_t bytes, void** out);
+// A second such buffer per (device, stream), for data a call keeps across
+// the launches that use scratch() (the range queries' counts and scan totals).
+kd_status aux_scratch(kd_stream stream, size_t bytes, void** out);
 
 // ---- kernel timing hook (kd_api.cpp) --------------------------------------
 // When enabled, launches of the named kernel are bracketed by hipEvents on

@@ -9,7 +9,8 @@
 // points from its offset on, in the order the traversal reaches them (split
 // planes only, so every point in range is visited).  The scan is three
 // kernels: per-block scans of 4,096 counts, one workgroup scanning the block
-// totals, and a pass adding them.
+// totals, and a pass adding them.  Counts and totals sit in the stream's
+// second scratch buffer (kept by the library like the first).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -114,13 +115,6 @@ __global__ __launch_bounds__(SCAN_T) void scan_add(int64_t* __restrict__ offsets
     if (blockIdx.x == 0 && threadIdx.x == 0) offsets[0] = 0;
 }
 
-struct DevFree {
-    void* p = nullptr;
-    ~DevFree() {
-        if (p) (void)hipFree(p);
-    }
-};
-
 kd_status range_all(kd_tree t, const float* in, int64_t Q, bool box, float maxRadius, int64_t* offsets,
                     int32_t* out_idx, int64_t capacity, int64_t* total, int flags, kd_stream stream,
                     const char* fn) {
@@ -143,14 +137,16 @@ kd_status range_all(kd_tree t, const float* in, int64_t Q, bool box, float maxRa
         return KD_OK;
     }
     const int64_t nb = (Q + SCAN_B - 1) / SCAN_B;
-    DevFree counts, bsum;
-    KD_HIP(hipMalloc(&counts.p, size_t(Q) * 4));
-    KD_HIP(hipMalloc(&bsum.p, size_t(nb) * 8));
-    uint32_t* cnt = static_cast<uint32_t*>(counts.p);
-    int64_t* bs = static_cast<int64_t*>(bsum.p);
+    // counts and block totals live across both traversals, which use the
+    // stream's main scratch: the second per-stream buffer holds them
+    const size_t cnt_b = (size_t(Q) * 4 + 255) & ~size_t(255);
+    void* aux = nullptr;
+    kd_status s = aux_scratch(stream, cnt_b + size_t(nb) * 8, &aux);
+    if (s != KD_OK) return s;
+    uint32_t* cnt = static_cast<uint32_t*>(aux);
+    int64_t* bs = reinterpret_cast<int64_t*>(static_cast<char*>(aux) + cnt_b);
     const float R2 = box ? 0.0f : maxRadius * maxRadius;  // binary32 product; +inf stays +inf
-    kd_status s = run_range(t, in, Q, box, R2, 0, nullptr, nullptr, cnt, nullptr, (flags & KD_RANGE_BOXES) == 0,
-                            stream);
+    s = run_range(t, in, Q, box, R2, 0, nullptr, nullptr, cnt, nullptr, (flags & KD_RANGE_BOXES) == 0, stream);
     if (s != KD_OK) return s;
     hipLaunchKernelGGL(scan_local, dim3(unsigned(nb)), dim3(SCAN_T), 0, st, cnt, Q, offsets + 1, bs);
     KD_HIP(hipGetLastError());
