@@ -400,3 +400,35 @@ def test_all_results_capacity_and_empty():
     off4, idx4 = kd.kd_box_search_all(empty, q - 1, q + 1)
     assert (off4 == 0).all() and idx4.numel() == 0
     empty.close()
+
+
+def test_all_results_offsets_at_scale(oracle_lib):
+    """The offsets of large query sets: 300K queries (73 scan blocks) against
+    the per-query counts, with sampled slices against the definition; and
+    17M queries over a small tree (more block totals than one pass of the
+    totals scan holds) against the counts."""
+    rng = np.random.default_rng(50)
+    P = rng.random((50_000, 3), dtype=np.float32)
+    Qs = rng.random((300_000, 3), dtype=np.float32)
+    tree = _build(P)
+    q = _t(Qs)
+    off, idx = kd.kd_radius_search_all(tree, q, 0.03)
+    c, _, _ = kd.kd_radius_search(tree, q, 0.03, 0)
+    torch.cuda.synchronize()
+    off, idx = off.cpu().numpy(), idx.cpu().numpy()
+    assert np.array_equal(np.diff(off), c.cpu().numpy().astype(np.int64)) and off[-1] == len(idx)
+    rows = rng.choice(len(Qs), 300, replace=False)
+    oc, _, _ = oracle_lib.radius(P, Qs[rows], 0.03, 0)
+    _, oi, _ = oracle_lib.radius(P, Qs[rows], 0.03, int(oc.max()))
+    for t, r in enumerate(rows):
+        assert np.array_equal(np.sort(idx[off[r]:off[r + 1]]), np.sort(oi[t][oi[t] >= 0])), f"row {r}"
+    tree.close()
+    small = kd.kd_build(_t(rng.random((64, 3), dtype=np.float32)))
+    print("[gpu] range all: 17M queries over 64 points", flush=True)
+    q2 = torch.rand((17_000_000, 3), device=_dev())
+    off2, idx2 = kd.kd_radius_search_all(small, q2, 0.05)
+    c2, _, _ = kd.kd_radius_search(small, q2, 0.05, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.diff(off2), c2.to(torch.int64)) and off2[0].item() == 0
+    assert off2[-1].item() == idx2.numel()
+    small.close()
