@@ -128,6 +128,9 @@ def test_build_validation():
         assert L.kd_build_host(pp, n, 3, ctypes.byref(h)) == kd.KD_EINVAL
         assert L.kd_build_order_host(pp, n, 3, None) == kd.KD_EINVAL
     assert L.kd_build(None, 4, 3, None, ctypes.byref(h)) == kd.KD_EINVAL
+    assert L.kd_build_ex(pp, 4, 3, 2, None, ctypes.byref(h)) == kd.KD_EINVAL
+    assert "split" in L.kd_last_error().decode()
+    assert L.kd_build_ex(pp, 4, 3, -1, None, ctypes.byref(h)) == kd.KD_EINVAL
     assert L.kd_build(pp, 4, 3, None, None) == kd.KD_EINVAL
     bad = pts.copy()
     bad[2, 1] = np.nan

@@ -157,6 +157,26 @@ def test_range_queries(oracle_lib):
     tree.close()
 
 
+@pytest.mark.parametrize("D", [2, 4])
+def test_range_queries_2d_4d(oracle_lib, D):
+    P = _data("aspect", 30_000, D, 60 + D)
+    Qs = _data("aspect", 4_000, D, 70 + D)
+    tree = _build(P)
+    _same_tree(oracle_lib, tree, P, f"range D={D}")
+    r = {2: 0.3, 4: 0.6}[D]
+    h = np.float32({2: 0.2, 4: 0.4}[D])
+    for flags in (0, kd.KD_RANGE_BOXES):
+        c, i, d = kd.kd_radius_search(tree, _t(Qs), r, 8, flags=flags)
+        bc, bi = kd.kd_box_search(tree, _t(Qs - h), _t(Qs + h), 8, flags=flags)
+        torch.cuda.synchronize()
+        oc, oi, od = oracle_lib.radius(P, Qs, r, 8)
+        ob, obi = oracle_lib.box(P, Qs - h, Qs + h, 8)
+        assert np.array_equal(c.cpu().numpy(), oc) and np.array_equal(i.cpu().numpy(), oi)
+        assert np.array_equal(d.cpu().numpy().view(np.uint32), od.view(np.uint32))
+        assert np.array_equal(bc.cpu().numpy(), ob) and np.array_equal(bi.cpu().numpy(), obi)
+    tree.close()
+
+
 def test_autotune_and_unsupported(oracle_lib):
     P = _data("clusters", 50_000, 3, 13)
     Qs = _data("clusters", 20_000, 3, 14)
