@@ -63,9 +63,9 @@ def src_hash(paths):
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_key: str, cur_hash: str, launches_units: float):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
-    was taken on the current kernel source; else None."""
+def load_counters(kernel_key: str, cur_hash: str):
+    """The committed rocprofv3 --pmc summary of the kernel, if it was taken on
+    the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel_key}_pmc.json")
     if not os.path.exists(path):
         return None
@@ -75,7 +75,14 @@ def load_traffic(kernel_key: str, cur_hash: str, launches_units: float):
         return None
     if d.get("source_hash") != cur_hash:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
+
+
+def load_traffic(kernel_key: str, cur_hash: str, launches_units: float):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source; else None."""
+    d = load_counters(kernel_key, cur_hash)
+    return None if d is None else d.get("hbm_bytes_per_launch")
 
 
 def host_cpu_model():
@@ -688,6 +695,10 @@ def main():
     achieved = alg_bytes / (kern_avg_ms / 1e3) / 1e9
     cur_hash = src_hash(["paper_2210_12859_amd/csrc/kd_traverse.hip", "paper_2210_12859_amd/csrc/kd_internal.h"])
     traffic = load_traffic(f"traverse_{args.workload}_k{k}", cur_hash, 1)
+    counters = load_counters(f"traverse_{args.workload}_k{k}", cur_hash)
+    # the secondary algorithmic total: node data plus each query read and its
+    # k results (index + squared distance) written by the same kernel
+    alg2 = alg_bytes + Q * (D * 4 + k * 8)
 
     out = {
         "metric": METRIC,
@@ -708,6 +719,12 @@ def main():
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "knn_persistent (stack-free traversal)",
                      "kernel_ms": kern_avg_ms, "alg_bytes_per_launch": alg_bytes,
+                     "secondary": {"alg_bytes_per_launch": alg2,
+                                   "frac": alg2 / (kern_avg_ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
+                                   "note": "node data + query reads + result writes"},
+                     "l2_hit_pct": counters.get("l2_hit_pct") if counters else None,
+                     "valu_issue_pct": (100.0 * counters["sq_insts_valu"] * 4 /
+                                        (1024 * kern_avg_ms * 1e-3 * 2.4e9)) if counters else None,
                      "source_hash": cur_hash},
         "visited_per_query": visited_total / Q,
         "nodes_visited_per_s": visited_total / (ms_per_step / 1e3),
