@@ -284,6 +284,37 @@ def bench_batched(kd, datagen, args):
                     for j, (oi, od) in zip(jobs, single))
     groups = batch.info()
     batch.close()
+    learned = None
+    if args.batch_learned:
+        # the same batch with a radius model per 3-D job of at least 2^16
+        # points (trained untimed on queries of the job's own distribution,
+        # another seed), default plans, against the plain default-plan replay
+        t0 = time.perf_counter()
+        models = []
+        for m, j in zip(jobs_meta, jobs):
+            if m["dim"] != 3 or m["n"] < (1 << 16):
+                continue
+            _, tq = datagen.job_arrays(dict(m, query_seed=m["query_seed"] + 10007))
+            model = kd.kd_radius_model_train(j["tree"], torch.from_numpy(tq).to(dev), j["k"], epochs=4,
+                                             batch=8192, seed=0)
+            j["model"] = model
+            models.append(model)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        lbatch = kd.Batch(jobs)
+        ms_l = timed(lambda: lbatch.run(stream), args.steps)
+        same = all(torch.equal(j["out_idx"], oi) and torch.equal(j["out_d2"].view(torch.int32), od.view(torch.int32))
+                   for j, (oi, od) in zip(jobs, single))
+        lbatch.close()
+        for j in jobs:
+            j.pop("model", None)
+        for model in models:
+            model.close()
+        learned = {"ms_per_step": ms_l, "value": total_q / (ms_l / 1e3), "unit": "queries/s",
+                   "speedup_vs_plain_default_options": ms_d / ms_l, "models": len(models),
+                   "train_s": train_s, "identical_to_single_calls": same}
+        log(f"batched learned: {ms_l:.3f} ms/step ({ms_d / ms_l:.3f}x the plain replay), {len(models)} models, "
+            f"identical {same}")
     for j in jobs:
         j["tree"].close()
     achieved = alg_bytes / (ms_b / 1e3) / 1e9
@@ -294,6 +325,7 @@ def bench_batched(kd, datagen, args):
             "tuned_options": [dict(dim=g[0], K=g[1], queries=g[2], **o) for g, o in zip(groups, tuned)],
             "ms_per_step_one_call_per_tree": ms_s, "speedup_vs_one_call_per_tree": ms_s / ms_b,
             "identical_to_single_calls": identical,
+            "learned": learned,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBPS, "alg_bytes_per_replay": alg_bytes,
                          "timed": "whole graph replay (sort, gather, traversal, hand-off of every group)"},
@@ -613,6 +645,8 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=8)
     ap.add_argument("--batch-jobs", type=int, default=512, help="trees in the batched measurement (0 = skip)")
     ap.add_argument("--batch-nmax", type=int, default=2000000, help="largest tree of the batched measurement")
+    ap.add_argument("--batch-learned", action="store_true",
+                    help="also time the batch with a radius model per large 3-D job")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--paper-grid", action="store_true",
