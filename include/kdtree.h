@@ -262,8 +262,9 @@ kd_status kd_knn_noalloc(kd_tree t, const float* queries, int64_t Q, int k, floa
  *               rows are kept, they cost more than they save.
  * An empty tree gives counts 0.  A NaN query has no point in range.
  * Scratch: the per-stream workspace of the kd_knn family (query records and
- * sort buffers, kd_workspace_size(Q)); queries are taken in Morton order.
- * Asynchronous on `stream`. */
+ * sort buffers: at most kd_workspace_size(Q) for radius queries; box queries
+ * add their centres, dim x 4 bytes per query); queries are taken in Morton
+ * order.  Asynchronous on `stream`. */
 #define KD_RANGE_BOXES 1
 kd_status kd_radius_search(kd_tree t, const float* queries, int64_t Q, float maxRadius, int cap,
                            int32_t* out_idx, float* out_d2, uint32_t* out_count, uint32_t* visited,
